@@ -1,0 +1,69 @@
+/*
+ * CPU oracle for memory-efficient label propagation (weighted Misra-Gries
+ * sketch LPA, arXiv 2411.19901).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load or call this library. The product
+ * (the HIP library under paper_2411_19901_amd/) shares no code with it and
+ * never links it.
+ *
+ * Conventions shared with the product only through the paper:
+ *   - undirected graph stored as symmetric CSR: row_ptr int32[n+1],
+ *     col int32[nnz]; weights fp32[nnz] (NULL = every weight 1.0);
+ *   - labels int32[n], initialised to the vertex id;
+ *   - sketch keys int32, sketch values fp32 (Section 5.1.2, Configuration).
+ */
+#ifndef LPA_ORACLE_H
+#define LPA_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* k-slot weighted Misra-Gries sketch (Section 4.1); slot s is empty iff
+ * val[s] == 0. */
+void orc_sketch_clear(int k, int32_t *key, float *val);
+void orc_sketch_accumulate(int k, int32_t *key, float *val, int32_t c, float w);
+int32_t orc_sketch_max_key(int k, const int32_t *key, const float *val,
+                           int32_t keep);
+/* clear, then feed len (label, weight) pairs in order; w NULL = unit. */
+void orc_sketch_feed(int k, int64_t len, const int32_t *labels, const float *w,
+                     int32_t *key, float *val);
+
+/* One synchronous (Jacobi) iteration of Algorithm 1's lpaMove.
+ * k >= 1: k-slot sketch; k == 0: exact argmax of Eq. 3 (dense accumulator).
+ * Reads C and act, writes C_next and act_next (act_next must be zeroed by
+ * the caller).  Returns the number of changed vertices; *scanned receives
+ * the number of CSR entries read by the neighbourhood scans. */
+int64_t orc_lpa_move(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                     const float *w, int k, int pickless, const int32_t *C,
+                     const uint8_t *act, int32_t *C_next, uint8_t *act_next,
+                     int nthreads, int64_t *scanned);
+
+/* Whole driver (Algorithm 1, lpa). Returns the number of iterations run,
+ * or -1 on bad arguments.  dN_trace / scanned_trace (may be NULL) receive
+ * max_iter entries each. */
+int orc_lpa_run(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                const float *w, int k, double tol, int max_iter, int rho,
+                int nthreads, int32_t *labels, int64_t *dN_trace,
+                int64_t *scanned_trace);
+
+/* The label each listed vertex would choose in one iteration, given C:
+ * out[q] = chosen label of verts[q] (the current label when it keeps it). */
+void orc_lpa_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                    const float *w, int k, int pickless, const int32_t *C,
+                    int64_t nv, const int32_t *verts, int32_t *out,
+                    int nthreads);
+
+/* Modularity Q of Eq. 1 (community-sum form) in fp64. */
+double orc_modularity(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                      const float *w, const int32_t *C);
+
+int orc_max_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
