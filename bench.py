@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the label-propagation hot path on one MI355X.
+
+Default workload: R-MAT scale 24, edge factor 16 (a, b, c, d = 0.57, 0.19,
+0.19, 0.05; symmetrised, self-loops and duplicates dropped; ~16.8M vertices,
+~0.52B CSR entries) with fp32 weights uniform in (0, 1], k = 8 sketch slots,
+asynchronous mode, tol 0.05, at most 20 iterations, pick-less every 8.
+
+One step = one full solve of that graph from iteration 0: lpa_reset +
+lpa_run (every iteration until convergence: neighbourhood scans, sketches,
+label updates, pruning flags, changed counters, convergence tests).  The
+graph is generated on the host, copied to HBM and binned by degree
+(lpa_init) before the timed region.
+
+value = CSR entries scanned over the timed steps / timed wall time, in
+GTEPS (1e9 edges per second).  roofline: the move kernel, with 12 bytes
+per scanned entry (column index 4 + weight 4 + gathered label 4) divided by
+the kernel time measured with HIP events on the library's stream, against
+the 8 TB/s HBM peak.  cpu_baseline: the CPU oracle (CSR-order sketches, all
+host threads) choosing labels for a random vertex sample of the same graph
+at iteration 0.
+"""
+import argparse
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LPA edges/sec per iteration (GTEPS) + % HBM roofline; batched graphs/s, p99"
+HBM_PEAK_GBPS = 8000.0
+BYTES_PER_EDGE = 12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel: str, workload: str, src_digest: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if a summary in
+    profiles/ matches this kernel, workload and source digest."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        text = open(os.path.join(pdir, name)).read()
+        m = {k: v.strip() for k, v in re.findall(r"^- (\w+): (.+)$", text, re.M)}
+        if (m.get("traffic_kernel") == kernel and m.get("traffic_workload") == workload
+                and m.get("source_digest") == src_digest and "traffic_bytes_per_launch" in m):
+            return float(m["traffic_bytes_per_launch"])
+    return None
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("move.hip", "lpa_internal.h"):
+        with open(os.path.join(ROOT, "paper_2411_19901_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(g, k, seconds, rng_seed=0):
+    """Oracle label choice (iteration 0, CSR order, k slots) on a random
+    vertex sample sized for about `seconds` of work on all host threads."""
+    import numpy as np
+    import oracle
+
+    deg = g.degrees()
+    verts_all = np.nonzero(deg > 0)[0].astype(np.int32)
+    rng = np.random.default_rng(rng_seed)
+    C = np.arange(g.n, dtype=np.int32)
+    nt = oracle.max_threads()
+    # calibrate on a small sample, then size the measured one
+    probe = rng.choice(verts_all, size=min(len(verts_all), 20000), replace=False)
+    t = time.perf_counter()
+    oracle.lpa_choose(g.row_ptr, g.col, g.w, k, True, C, probe)
+    dt = max(time.perf_counter() - t, 1e-3)
+    rate = deg[probe].sum() / dt
+    target_edges = rate * seconds
+    frac = min(1.0, target_edges / max(1, g.nnz))
+    m = max(1000, int(frac * len(verts_all)))
+    sample = np.sort(rng.choice(verts_all, size=min(m, len(verts_all)), replace=False))
+    edges = int(deg[sample].sum())
+    t = time.perf_counter()
+    oracle.lpa_choose(g.row_ptr, g.col, g.w, k, True, C, sample)
+    dt = time.perf_counter() - t
+    return {"value": round(edges / dt / 1e9, 4), "unit": "GTEPS", "cores": int(nt),
+            "kind": "oracle",
+            "sample": f"{len(sample)} uniformly sampled non-isolated vertices ({edges} CSR entries, "
+                      f"{100.0 * edges / g.nnz:.1f}% of the graph), one iteration-0 label choice each, "
+                      f"k={k}, {dt:.1f} s on {nt} threads"}
+
+
+def build_graph(args):
+    from paper_2411_19901_amd import inputs
+    t = time.perf_counter()
+    if args.graph == "rmat":
+        g = inputs.rmat(args.scale, 16, seed=args.scale)
+        name = f"rmat{args.scale}-ef16"
+    elif args.graph == "grid":
+        g = inputs.grid(4096, 4096, 0.05, 0.01, seed=4096)
+        name = "grid4096-del5-rw1"
+    elif args.graph == "sbm1":
+        g = inputs.sbm1(1)
+        name = "sbm1"
+    else:
+        raise SystemExit(f"unknown graph {args.graph}")
+    if args.weights == "uniform":
+        g = inputs.with_uniform_weights(g, args.scale if args.graph == "rmat" else 7)
+        name += "-wU(0,1]"
+    else:
+        name += "-w1"
+    log(f"[bench] generated {name}: n={g.n} nnz={g.nnz} in {time.perf_counter() - t:.1f}s")
+    return g, name
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--graph", default="rmat", choices=["rmat", "grid", "sbm1"])
+    ap.add_argument("--scale", type=int, default=24)
+    ap.add_argument("--weights", default="uniform", choices=["uniform", "unit"])
+    ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--mode", default="async", choices=["async", "det"])
+    ap.add_argument("--max-iter", type=int, default=20)
+    ap.add_argument("--tol", type=float, default=0.05)
+    ap.add_argument("--lane-max-degree", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "design is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2411_19901_amd import lpa
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    lpa.load()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    g, gname = build_graph(args)
+    workload = f"{gname}-{args.mode}-k{args.k}"
+
+    t = time.perf_counter()
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev) if g.w is not None else None
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t
+    stream = torch.cuda.current_stream(dev)
+    free0, _ = torch.cuda.mem_get_info(dev)
+    t = time.perf_counter()
+    solver = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
+                     mode=args.mode, lane_max_degree=args.lane_max_degree,
+                     check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
+    torch.cuda.synchronize()
+    init_ms = (time.perf_counter() - t) * 1e3
+    free1, _ = torch.cuda.mem_get_info(dev)
+    core_bytes, _ = solver.memory()
+    solver.profile(True)
+    log(f"[bench] lpa_init {init_ms:.1f} ms; library bytes/vertex {core_bytes / g.n:.2f}")
+
+    for i in range(args.warmup):
+        solver.reset()
+        it = solver.run()
+        log(f"[bench] warmup {i}: {it} iterations")
+
+    edges_total = 0
+    kernel_bytes = 0
+    kernel_ms = 0.0
+    launches = 0
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_step = []
+    for s in range(args.steps):
+        ts = time.perf_counter()
+        solver.reset()
+        it = solver.run()
+        dn, sc = solver.trace()
+        ms = solver.move_ms()
+        per_step.append((time.perf_counter() - ts) * 1e3)
+        iters.append(it)
+        edges_total += int(sc.sum())
+        kernel_bytes += BYTES_PER_EDGE * int(sc.sum())
+        kernel_ms += float(ms.sum())
+        launches += len(ms)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f}s; iterations {iters}")
+
+    labels = solver.labels(device=True)
+    tq = time.perf_counter()
+    q = solver.modularity()
+    mod_ms = (time.perf_counter() - tq) * 1e3
+    dn, sc = solver.trace()
+    ms = solver.move_ms()
+
+    achieved = kernel_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
+    digest = source_digest()
+    traffic = traffic_from_profiles(f"k_move<{args.k},{str(args.mode == 'async').lower()}>",
+                                    workload, digest)
+    result = {
+        "metric": METRIC,
+        "value": round(edges_total / elapsed / 1e9, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": g.n, "nnz": g.nnz, "k": args.k, "mode": args.mode,
+                   "tol": args.tol, "max_iter": args.max_iter, "rho": 8,
+                   "step": "lpa_reset + lpa_run (all iterations to convergence)"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": f"k_move<{args.k},{str(args.mode == 'async').lower()}>",
+                     "bytes_per_edge": BYTES_PER_EDGE, "launches": launches,
+                     "avg_launch_ms": round(kernel_ms / max(launches, 1), 4),
+                     "source_digest": digest},
+        "iterations": iters[-1],
+        "iter0": {"scanned": int(sc[0]) if len(sc) else 0,
+                  "move_ms": round(float(ms[0]), 4) if len(ms) else None,
+                  "GBps": round(BYTES_PER_EDGE * int(sc[0]) / (float(ms[0]) * 1e-3) / 1e9, 1)
+                  if len(ms) and ms[0] > 0 else None},
+        "trace": {"changed": dn.tolist(), "scanned": sc.tolist(),
+                  "move_ms": [round(float(x), 4) for x in ms]},
+        "modularity": round(q, 6),
+        "modularity_ms": round(mod_ms, 3),
+        "init_ms": round(init_ms, 2),
+        "h2d_s": round(h2d_s, 3),
+        "bytes_per_vertex": round(core_bytes / g.n, 3),
+        "hipmeminfo_bytes_per_vertex": round((free0 - free1) / g.n, 3),
+        "gpu": torch.cuda.get_device_name(dev),
+    }
+    del labels
+    solver.close()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a vertex sample")
+        result["cpu_baseline"] = cpu_baseline(g, args.k, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

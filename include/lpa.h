@@ -1,0 +1,201 @@
+/*
+ * lpa.h — C ABI of the MI355X (gfx950) label-propagation library
+ * (liblpa.so): memory-efficient community detection with a k-slot weighted
+ * Misra-Gries sketch per vertex, after arXiv 2411.19901.
+ *
+ * The method (paper Section 4; Algorithm 1 lpa / lpaMove; Algorithm 2
+ * sketchAccumulate): every label starts as the vertex id; in each iteration
+ * every unprocessed vertex streams its CSR neighbour list, keeps a k-slot
+ * weighted Misra-Gries sketch of the neighbours' labels (Section 4.1) and
+ * adopts the heaviest sketch label (Section 4.4, single scan).  Every rho
+ * iterations from the first a vertex may only move to a lower label
+ * (pick-less, Section 4.5).  Changed vertices mark their neighbours
+ * unprocessed; the run stops when a non-pick-less iteration changes fewer
+ * than tol * N labels, or after max_iter iterations (Algorithm 1, lpa).
+ *
+ * Modes:
+ *   LPA_MODE_DET    synchronous (Jacobi) updates; every sketch is fed in CSR
+ *                   order.  Labels are bit-identical to the sequential CPU
+ *                   definition of the algorithm, independent of launch
+ *                   geometry, bin thresholds and scheduling.
+ *   LPA_MODE_ASYNC  labels and flags are updated in place while the
+ *                   iteration runs (as the paper's GPU implementation
+ *                   does); high-degree vertices use partial sketches that
+ *                   are merged (Section 4.3).  Results depend on scheduling.
+ *
+ * Readings of points the paper leaves open (shared with the CPU
+ * definition; listed in the design doc): the sketch decrement subtracts
+ * d = min(w, smallest slot) and inserts the residue w - d (identical to the
+ * paper's rule on unit weights); k = 1 is the same rule with one slot;
+ * ties go to the lowest label; an empty sketch keeps the label; a vertex
+ * blocked by pick-less still counts as processed; N = |V| and the
+ * convergence test is strict.
+ *
+ * Conventions for every call:
+ *   - Every function returns an lpa_status code; no call aborts or throws.
+ *   - Device pointers are HIP device (or managed) pointers on the device
+ *     current at lpa_init.  Graph arrays are BORROWED: the caller owns them,
+ *     they must stay valid and unmodified until lpa_free.
+ *   - Work is enqueued on the handle's stream.  Calls that return host
+ *     values synchronise that stream first.
+ *   - A handle is not re-entrant; separate handles may be used from
+ *     separate threads on separate streams.
+ *   - After a HIP runtime error the handle is poisoned: every later call
+ *     except lpa_free / lpa_last_error returns LPA_ERR_HIP.
+ *   - All device memory the library needs is allocated in lpa_init (plus
+ *     an fp64 scratch on the first lpa_modularity call); iterations
+ *     allocate nothing.
+ */
+#ifndef LPA_H
+#define LPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lpa_status {
+  LPA_OK = 0,
+  LPA_ERR_ARG = 1,         /* null pointer, bad k / tol / max_iter / rho / size */
+  LPA_ERR_GRAPH = 2,       /* invalid CSR, weights or labels (see LPA_VALIDATE) */
+  LPA_ERR_UNSUPPORTED = 3, /* k not one of 1, 2, 4, 8, 16, 32; unknown mode */
+  LPA_ERR_NOMEM = 4,       /* device allocation failed */
+  LPA_ERR_HIP = 5,         /* HIP runtime error; the handle is now poisoned */
+  LPA_ERR_STATE = 6        /* handle in the wrong state for this call */
+} lpa_status;
+
+/* mode (low byte) and option flags for lpa_config.flags */
+#define LPA_MODE_DET 0u
+#define LPA_MODE_ASYNC 1u
+#define LPA_MODE_MASK 0xFFu
+/* Check the CSR on the device in lpa_init: row_ptr[0] == 0, nondecreasing,
+ * row_ptr[n] == nnz, 0 <= col < n, weights finite and > 0.  Without it an
+ * invalid graph is undefined behaviour (out-of-range reads).  Symmetry is
+ * expected but never checked. */
+#define LPA_VALIDATE 0x100u
+
+/* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji). */
+typedef struct lpa_graph {
+  int32_t n;               /* number of vertices, 0 <= n < 2^31 - 1 */
+  int64_t nnz;             /* number of CSR entries (directed), < 2^31 */
+  const int32_t *row_ptr;  /* device int32[n+1] */
+  const int32_t *col_idx;  /* device int32[nnz], neighbour ids */
+} lpa_graph;
+
+typedef struct lpa_config {
+  uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC, | LPA_VALIDATE */
+  int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
+  void *stream;            /* hipStream_t for all work; NULL = null stream */
+  int32_t lane_max_degree; /* vertices with degree <= this run one lane per
+                              vertex, higher degrees cooperatively;
+                              0 = default for the mode.  Never changes
+                              LPA_MODE_DET results. */
+  int32_t check_every;     /* lpa_run reads the convergence flag on the host
+                              every this many iterations and stops launching
+                              once it is set; 0 = enqueue all max_iter
+                              iterations (finished ones exit on the device)
+                              and synchronise once */
+  int32_t reserved[6];     /* must be zero */
+} lpa_config;
+
+typedef struct lpa_handle lpa_handle;
+
+/* Fill *cfg with the defaults (det mode, rho 8, null stream, validation on). */
+void lpa_config_default(lpa_config *cfg);
+
+/* Create a handle for graph g.
+ *   weights  device fp32[nnz] edge weights, symmetric, finite, > 0;
+ *            NULL = every weight 1.0 (borrowed like the graph)
+ *   k        sketch slots: 1 (weighted Boyer-Moore), 2, 4, 8, 16 or 32
+ *   tol      tau in [0, 1]: stop when dN / N < tol in a non-pick-less iteration
+ *   max_iter maximum iterations, >= 0
+ *   seed     recorded only; no mode draws random numbers
+ *   cfg      NULL = lpa_config_default
+ * Allocates the label, flag, bin and counter arrays on the current device,
+ * bins the vertices by degree, and sets labels to vertex ids.
+ * On success *out receives the handle; on failure *out is NULL. */
+int lpa_init(const lpa_graph *g, const float *weights, int k, double tol,
+             int max_iter, uint64_t seed, const lpa_config *cfg,
+             lpa_handle **out);
+
+/* Return the handle to iteration 0 (labels = ids, all vertices unprocessed,
+ * traces cleared) without re-binning.  Enqueued; does not synchronise. */
+int lpa_reset(lpa_handle *h);
+
+/* Run one iteration (Algorithm 1, one lpaMove plus its convergence test)
+ * and synchronise.  *changed = dN of that iteration; *done = 1 once the
+ * run has finished (converged or max_iter reached).  A call on a finished
+ * handle does nothing and reports changed = 0, done = 1.  Either output
+ * pointer may be NULL. */
+int lpa_step(lpa_handle *h, int64_t *changed, int *done);
+
+/* Run iterations until convergence or max_iter, then synchronise.
+ * *iterations (may be NULL) = total iterations run since init / reset. */
+int lpa_run(lpa_handle *h, int *iterations);
+
+/* Modularity Q of Eq. 1, community-sum form, accumulated in fp64.
+ * labels: device int32[n] with values in [0, n), or NULL for the handle's
+ * current labels.  Returns LPA_ERR_GRAPH (and leaves *q unset) if a label
+ * is out of range.  Synchronises. */
+int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q);
+
+/* Copy the current labels (int32[n]) to out, a host pointer if out_is_host
+ * is nonzero, else a device pointer.  Synchronises. */
+int lpa_get_labels(lpa_handle *h, int32_t *out, int out_is_host);
+
+/* Per-iteration counters of the current run: changed[i] = dN and
+ * scanned[i] = CSR entries read by the neighbourhood scans of iteration i,
+ * for i < *count = iterations run (at most capacity are written; either
+ * array may be NULL).  Synchronises. */
+int lpa_get_trace(lpa_handle *h, int64_t *changed, int64_t *scanned,
+                  int capacity, int *count);
+
+/* Checkpoint: copy out labels int32[n] and the unprocessed flags uint8[n]
+ * that the next iteration will read, plus the next iteration index
+ * (flags of degree-0 vertices are unspecified).  Host pointers if is_host.
+ * Synchronises. */
+int lpa_get_state(lpa_handle *h, int32_t *labels, uint8_t *unprocessed,
+                  int *iteration, int is_host);
+
+/* Restore a checkpoint into a handle built on the same graph and
+ * parameters: labels (values in [0, n), checked -> LPA_ERR_GRAPH),
+ * unprocessed flags (nonzero = unprocessed) and the next iteration index in
+ * [0, max_iter].  Traces of earlier iterations read as zero.  In
+ * LPA_MODE_DET the continued run is bit-identical to an uninterrupted one.
+ * Synchronises. */
+int lpa_set_state(lpa_handle *h, const int32_t *labels,
+                  const uint8_t *unprocessed, int iteration, int is_host);
+
+/* Device bytes allocated by the handle: core = everything the iterations
+ * use (labels, flags, bins, counters; excludes the caller's graph and
+ * weights), eval = fp64 modularity scratch (0 before the first
+ * lpa_modularity). Either pointer may be NULL. */
+int lpa_memory(const lpa_handle *h, size_t *core_bytes, size_t *eval_bytes);
+
+/* Kernel timing: when enabled, HIP events are recorded on the handle's
+ * stream immediately before and after the move kernel (the neighbourhood
+ * scan, sketch and label update) of every iteration.  Enabling it creates
+ * the events; it is off by default. */
+int lpa_profile(lpa_handle *h, int enable);
+
+/* Duration in milliseconds of the move kernel of each iteration of the
+ * current run (move_ms[i] for i < *count = iterations run; at most
+ * capacity written).  LPA_ERR_STATE when profiling is off.  Synchronises. */
+int lpa_get_profile(lpa_handle *h, float *move_ms, int capacity, int *count);
+
+/* Release the handle and its device memory (synchronises its stream first).
+ * NULL is accepted. */
+int lpa_free(lpa_handle *h);
+
+/* Static description of a status code. */
+const char *lpa_error_string(int code);
+/* Description of the last error on h ("" when none); valid until the next
+ * call on h. */
+const char *lpa_last_error(const lpa_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPA_H */

@@ -51,25 +51,46 @@ double gg_uniform(uint64_t seed, uint64_t a, uint64_t b) {
 /* CSR assembly                                                          */
 /* ------------------------------------------------------------------ */
 
-static int cmp_i32(const void *x, const void *y) {
-  int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
-  return (a > b) - (a < b);
+static void insertion_sort(int32_t *a, int64_t len) {
+  for (int64_t i = 1; i < len; ++i) {
+    int32_t x = a[i];
+    int64_t j = i - 1;
+    while (j >= 0 && a[j] > x) {
+      a[j + 1] = a[j];
+      --j;
+    }
+    a[j + 1] = x;
+  }
 }
 
+/* in-place quicksort of int32 (median of three, small parts by insertion) */
 static void sort_row(int32_t *a, int64_t len) {
-  if (len < 24) {
-    for (int64_t i = 1; i < len; ++i) {
-      int32_t x = a[i];
-      int64_t j = i - 1;
-      while (j >= 0 && a[j] > x) {
-        a[j + 1] = a[j];
-        --j;
-      }
-      a[j + 1] = x;
+  while (len > 24) {
+    int32_t x = a[0], y = a[len / 2], z = a[len - 1];
+    int32_t p = x < y ? (y < z ? y : (x < z ? z : x)) : (x < z ? x : (y < z ? z : y));
+    int64_t i = 0, j = len - 1;
+    for (;;) {
+      while (a[i] < p) ++i;
+      while (a[j] > p) --j;
+      if (i >= j) break;
+      int32_t t = a[i];
+      a[i] = a[j];
+      a[j] = t;
+      ++i;
+      --j;
     }
-  } else {
-    qsort(a, (size_t)len, sizeof(int32_t), cmp_i32);
+    /* recurse into the smaller side, loop on the larger */
+    int64_t left = j + 1;
+    if (left < len - left) {
+      sort_row(a, left);
+      a += left;
+      len -= left;
+    } else {
+      sort_row(a + left, len - left);
+      len = left;
+    }
   }
+  insertion_sort(a, len);
 }
 
 /* tmp holds, for each vertex i, deg0[i] unsorted neighbour ids starting at
@@ -220,28 +241,31 @@ int gg_sbm(int32_t nb, const int32_t *start, double p_in, double p_out,
 /* R-MAT (recursive matrix) graphs                                        */
 /* ------------------------------------------------------------------ */
 
-static inline void rmat_edge(int scale, double a, double b, double c,
-                             uint64_t seed, uint64_t e, int32_t *pu,
-                             int32_t *pv) {
+/* One counter hash per sampled edge seeds a splitmix64 stream; each level
+ * consumes 32 bits compared against 32-bit fixed-point thresholds. */
+static inline void rmat_edge(int scale, uint32_t ta, uint32_t tab, uint32_t tabc,
+                             uint64_t seed, uint64_t e, int32_t *pu, int32_t *pv) {
   uint32_t u = 0, v = 0;
-  double ab = a + b, abc = a + b + c;
+  uint64_t state = gg_hash3(seed, e, 0x5241544dull), bits = 0;
   for (int lv = 0; lv < scale; ++lv) {
-    double r = u01(gg_hash3(seed, e, (uint64_t)lv));
-    uint32_t ub, vb;
-    if (r < a) {
-      ub = 0; vb = 0;
-    } else if (r < ab) {
-      ub = 0; vb = 1;
-    } else if (r < abc) {
-      ub = 1; vb = 0;
-    } else {
-      ub = 1; vb = 1;
+    if ((lv & 1) == 0) {
+      state += 0x9E3779B97F4A7C15ull;
+      bits = mix64(state);
     }
+    uint32_t r = (lv & 1) ? (uint32_t)(bits >> 32) : (uint32_t)bits;
+    uint32_t ub = r >= tab, vb = (r >= ta && r < tab) || r >= tabc;
     u = (u << 1) | ub;
     v = (v << 1) | vb;
   }
   *pu = (int32_t)u;
   *pv = (int32_t)v;
+}
+
+static uint32_t fixed32(double p) {
+  double x = p * 4294967296.0;
+  if (x >= 4294967295.0) return 0xFFFFFFFFu;
+  if (x <= 0.0) return 0u;
+  return (uint32_t)x;
 }
 
 /* 2^scale vertices, edge_factor * 2^scale sampled edges; self-loops and
@@ -251,11 +275,12 @@ int gg_rmat(int scale, int edge_factor, double a, double b, double c,
   if (scale < 1 || scale > 30) return -2;
   int32_t n = (int32_t)1 << scale;
   int64_t m = (int64_t)edge_factor << scale;
+  const uint32_t ta = fixed32(a), tab = fixed32(a + b), tabc = fixed32(a + b + c);
   int64_t *off = (int64_t *)calloc((size_t)n + 2, sizeof(int64_t));
 #pragma omp parallel for schedule(static)
   for (int64_t e = 0; e < m; ++e) {
     int32_t u, v;
-    rmat_edge(scale, a, b, c, seed, (uint64_t)e, &u, &v);
+    rmat_edge(scale, ta, tab, tabc, seed, (uint64_t)e, &u, &v);
     if (u == v) continue;
     __atomic_fetch_add(&off[u + 1], 1, __ATOMIC_RELAXED);
     __atomic_fetch_add(&off[v + 1], 1, __ATOMIC_RELAXED);
@@ -268,7 +293,7 @@ int gg_rmat(int scale, int edge_factor, double a, double b, double c,
 #pragma omp parallel for schedule(static)
   for (int64_t e = 0; e < m; ++e) {
     int32_t u, v;
-    rmat_edge(scale, a, b, c, seed, (uint64_t)e, &u, &v);
+    rmat_edge(scale, ta, tab, tabc, seed, (uint64_t)e, &u, &v);
     if (u == v) continue;
     tmp[__atomic_fetch_add(&cur[u], 1, __ATOMIC_RELAXED)] = v;
     tmp[__atomic_fetch_add(&cur[v], 1, __ATOMIC_RELAXED)] = u;

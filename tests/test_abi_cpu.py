@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads and
+exports every function include/lpa.h declares; argument errors that are
+caught before any device work return their documented codes."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2411_19901_amd import lpa
+
+
+def test_library_exports_every_header_function():
+    L = lpa.load()
+    names = lpa.header_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_error_strings():
+    L = lpa.load()
+    for code in range(0, 7):
+        assert L.lpa_error_string(code)
+    assert L.lpa_error_string(99) == b"unknown status"
+
+
+def test_config_default():
+    cfg = lpa.lpa_config_default()
+    assert cfg.flags == lpa.LPA_MODE_DET | lpa.LPA_VALIDATE
+    assert cfg.rho == 8 and not cfg.stream and cfg.lane_max_degree == 0
+    assert cfg.check_every == 0 and list(cfg.reserved) == [0] * 6
+
+
+def _init(**kw):
+    L = lpa.load()
+    g = lpa.LpaGraph(kw.get("n", 4), kw.get("nnz", 0), kw.get("rp", 0), kw.get("col", 0))
+    cfg = lpa.lpa_config_default()
+    for k, v in kw.get("cfg", {}).items():
+        setattr(cfg, k, v)
+    h = ctypes.c_void_p(123)
+    rc = L.lpa_init(ctypes.byref(g) if kw.get("g", True) else None, None, kw.get("k", 8),
+                    kw.get("tol", 0.05), kw.get("max_iter", 20), 0, ctypes.byref(cfg),
+                    ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(g=False), lpa.LPA_ERR_ARG),
+    (dict(n=-1), lpa.LPA_ERR_ARG),
+    (dict(n=4, rp=0), lpa.LPA_ERR_ARG),              # null row_ptr with n > 0
+    (dict(n=0, nnz=3), lpa.LPA_ERR_ARG),
+    (dict(n=4, rp=8, nnz=2**31), lpa.LPA_ERR_ARG),   # nnz beyond int32 offsets
+    (dict(n=4, rp=8, tol=-0.1), lpa.LPA_ERR_ARG),
+    (dict(n=4, rp=8, tol=float("nan")), lpa.LPA_ERR_ARG),
+    (dict(n=4, rp=8, max_iter=-1), lpa.LPA_ERR_ARG),
+    (dict(n=4, rp=8, cfg=dict(rho=-2)), lpa.LPA_ERR_ARG),
+    (dict(n=4, rp=8, k=3), lpa.LPA_ERR_UNSUPPORTED),
+    (dict(n=4, rp=8, k=64), lpa.LPA_ERR_UNSUPPORTED),
+    (dict(n=4, rp=8, cfg=dict(flags=7)), lpa.LPA_ERR_UNSUPPORTED),
+])
+def test_init_argument_errors(kw, code):
+    rc, h = _init(**kw)
+    assert rc == code
+    assert not h.value  # *out is cleared on failure
+
+
+def test_null_handle_calls():
+    L = lpa.load()
+    assert L.lpa_free(None) == lpa.LPA_OK
+    assert L.lpa_step(None, None, None) == lpa.LPA_ERR_ARG
+    assert L.lpa_run(None, None) == lpa.LPA_ERR_ARG
+    assert L.lpa_last_error(None) == b""
