@@ -133,6 +133,45 @@ __global__ void k_bin_scatter(int n, const int32_t *rp, int lane_max, int ncls, 
 }
 
 // --- iteration epilogue ------------------------------------------------------
+// Async hub segments: pbase[h] = sum over earlier hubs of ceil(deg / S);
+// pbase[n_hubs] (also written to *total) = number of segments.  One block.
+__global__ void k_hub_plan(const int32_t *order, int n_hubs, const int32_t *rp, int S,
+                           int32_t *pbase, int *total) {
+  __shared__ long long part[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (n_hubs + nt - 1) / nt;
+  const int h0 = t * per, h1 = min(n_hubs, h0 + per);
+  long long s = 0;
+  for (int h = h0; h < h1; ++h) {
+    const int v = order[h];
+    s += (rp[v + 1] - rp[v] + S - 1) / S;
+  }
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    long long acc = 0;
+    for (int i = 0; i < nt; ++i) {
+      const long long x = part[i];
+      part[i] = acc;
+      acc += x;
+    }
+    pbase[n_hubs] = (int32_t)acc;
+    *total = (int)acc;
+  }
+  __syncthreads();
+  long long acc = part[t];
+  for (int h = h0; h < h1; ++h) {
+    pbase[h] = (int32_t)acc;
+    const int v = order[h];
+    acc += (rp[v + 1] - rp[v] + S - 1) / S;
+  }
+}
+
+__global__ void k_fill_seg_hub(const int32_t *pbase, int n_hubs, int32_t *seg_hub) {
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < n_hubs; h += gridDim.x * blockDim.x)
+    for (int q = pbase[h]; q < pbase[h + 1]; ++q) seg_hub[q] = h;
+}
+
 // ctl[0] = done, ctl[1] = iterations run
 __global__ void k_finish(const unsigned long long *dN, int iter, int n, double tol, int rho,
                          int max_iter, int *ctl) {
@@ -275,13 +314,20 @@ struct lpa_handle {
   int32_t *C[2] = {nullptr, nullptr};    // det: labels of even / odd iterations; async: C[0]
   uint8_t *act[2] = {nullptr, nullptr};   // det: flags of even / odd iterations; async: act[0]
   int32_t *order = nullptr;
+  int32_t *hub_pbase = nullptr;  // async: [n_hubs + 1]
+  int32_t *seg_hub = nullptr;    // async: [n_seg]
+  uint8_t *hub_act = nullptr;    // async: [n_hubs]
+  int32_t *part_key = nullptr;   // async: [n_seg * k]
+  float *part_val = nullptr;     // async: [n_seg * k]
+  int n_seg = 0;
+  int grid_merge = 1;
   unsigned long long *dN = nullptr;       // [max(1, max_iter)]
   unsigned long long *scanned = nullptr;  // [max(1, max_iter)]
   int *ctl = nullptr;                     // [0] done, [1] iterations, [2] error bits, [3..] totals
   double *mod_tot = nullptr;
   double *mod_acc = nullptr;
 
-  int n_hubs = 0, n_lane = 0, total_items = 0;
+  int n_hubs = 0, n_lane = 0;
   int grid_move = 1;
   int iter = 0;  // next iteration index (host view)
   bool finished = false;
@@ -347,7 +393,7 @@ int check_ready(lpa_handle *h) {
   return LPA_OK;
 }
 
-int default_lane_max(bool async_mode) { return async_mode ? 64 : 128; }
+int default_lane_max(bool async_mode) { return async_mode ? 1024 : 1024; }
 
 // Enqueue iteration state for iteration 0.
 int enqueue_reset(lpa_handle *h) {
@@ -393,7 +439,13 @@ int enqueue_iteration(lpa_handle *h, int l) {
   a.order = h->order;
   a.n_hubs = h->n_hubs;
   a.n_lane = h->n_lane;
-  a.total_items = h->total_items;
+  a.seg_len = h->lane_max;
+  a.n_seg = h->async_mode ? h->n_seg : 0;
+  a.seg_hub = h->seg_hub;
+  a.hub_pbase = h->hub_pbase;
+  a.hub_act = h->hub_act;
+  a.part_key = h->part_key;
+  a.part_val = h->part_val;
   a.iter = l;
   a.pickless = (h->rho > 0 && l % h->rho == 0) ? 1 : 0;
   a.dN = h->dN;
@@ -401,8 +453,8 @@ int enqueue_iteration(lpa_handle *h, int l) {
   a.done = h->ctl;
   const bool prof = !h->ev_beg.empty();
   if (prof) HIP_TRY(h, hipEventRecord(h->ev_beg[l], h->stream));
-  if (h->total_items > 0) {
-    hipError_t e = launch_move(h->k, h->async_mode, a, h->grid_move, h->stream);
+  if (h->n_hubs + h->n_lane > 0) {
+    hipError_t e = launch_move(h->k, h->async_mode, a, h->grid_move, h->grid_merge, h->stream);
     if (e != hipSuccess) return fail_hip(h, e, "move kernel launch");
   }
   if (prof) HIP_TRY(h, hipEventRecord(h->ev_end[l], h->stream));
@@ -565,7 +617,27 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     if (!ok) return bail(LPA_ERR_HIP);
     h->n_hubs = totals[0];
     h->n_lane = totals[1];
-    h->total_items = h->n_hubs + (h->n_lane + kWave - 1) / kWave;
+  }
+
+  // async: split every hub into segments of lane_max entries
+  if (h->async_mode && h->n_hubs > 0) {
+    if ((rc = dev_alloc(h, &h->hub_pbase, (size_t)h->n_hubs + 1)) != LPA_OK) return bail(rc);
+    if ((rc = dev_alloc(h, &h->hub_act, (size_t)h->n_hubs)) != LPA_OK) return bail(rc);
+    hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(1024), 0, h->stream, (const int32_t *)h->order,
+                       h->n_hubs, h->row_ptr, h->lane_max, h->hub_pbase, h->ctl + 5);
+    int nseg = 0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&nseg, h->ctl + 5, sizeof(int), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return bail(LPA_ERR_HIP);
+    h->n_seg = nseg;
+    if ((rc = dev_alloc(h, &h->seg_hub, (size_t)nseg)) != LPA_OK) return bail(rc);
+    if ((rc = dev_alloc(h, &h->part_key, (size_t)nseg * k)) != LPA_OK) return bail(rc);
+    if ((rc = dev_alloc(h, &h->part_val, (size_t)nseg * k)) != LPA_OK) return bail(rc);
+    hipLaunchKernelGGL(k_fill_seg_hub, dim3(grid_for(h->n_hubs)), dim3(kAuxBlock), 0, h->stream,
+                       (const int32_t *)h->hub_pbase, h->n_hubs, h->seg_hub);
+    if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
   }
 
   int cus = 0;
@@ -573,9 +645,15 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     return bail(LPA_ERR_HIP);
   const int waves_per_block = kBlock / kWave;
   int grid = cus * move_blocks_per_cu(k, h->async_mode);
-  const int need = (h->total_items + waves_per_block - 1) / waves_per_block;
+  const int units = (h->async_mode ? h->n_seg : 0) + h->n_lane;
+  const int items = (h->async_mode ? 0 : h->n_hubs) + (units + kWave - 1) / kWave;
+  const int need = (items + waves_per_block - 1) / waves_per_block;
   if (grid > need) grid = need;
   h->grid_move = grid > 0 ? grid : 1;
+  const int merge_items = (h->n_hubs + kWave - 1) / kWave;
+  int mg = (merge_items + waves_per_block - 1) / waves_per_block;
+  if (mg > cus * 4) mg = cus * 4;
+  h->grid_merge = mg > 0 ? mg : 1;
 
   if ((rc = enqueue_reset(h)) != LPA_OK) return bail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LPA_ERR_HIP);

@@ -36,9 +36,16 @@ struct MoveArgs {
   uint8_t *act_cur;        // unprocessed flags read (and cleared) this iteration
   uint8_t *act_next;       // flags set for the next iteration (async: == act_cur)
   const int32_t *order;    // vertex ids: hubs (desc degree), then lane vertices
-  int32_t n_hubs;
-  int32_t n_lane;
-  int32_t total_items;     // n_hubs + ceil(n_lane / 64)
+  int32_t n_hubs;          // vertices of degree > seg_len
+  int32_t n_lane;          // vertices of degree 1 .. seg_len
+  int32_t seg_len;         // S: longest run of CSR entries one lane scans
+  // LPA_MODE_ASYNC hub segments and partial sketches
+  int32_t n_seg;                // segment units (0 in det mode)
+  const int32_t *seg_hub;       // [n_seg] hub index of each segment
+  const int32_t *hub_pbase;     // [n_hubs + 1] first segment of each hub
+  uint8_t *hub_act;             // [n_hubs] flags snapshot of this iteration
+  int32_t *part_key;            // [n_seg * k]
+  float *part_val;              // [n_seg * k]
   int32_t iter;
   int32_t pickless;
   unsigned long long *dN;       // [max_iter]
@@ -47,7 +54,7 @@ struct MoveArgs {
 };
 
 hipError_t launch_move(int k, bool async_mode, const MoveArgs &a, int grid,
-                       hipStream_t s);
+                       int merge_grid, hipStream_t s);
 int move_blocks_per_cu(int k, bool async_mode);
 
 }  // namespace lpa

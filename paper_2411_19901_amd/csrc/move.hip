@@ -1,12 +1,27 @@
 // lpaMove kernels for gfx950 (paper Algorithm 1, lpaMove; Algorithm 2,
 // sketchAccumulate; Sections 4.1-4.5).
 //
-// One persistent kernel per iteration.  Work items are the hubs (one
-// wavefront per vertex, in decreasing degree) followed by chunks of 64
-// lower-degree vertices (one lane per vertex), dealt to the wavefronts
-// round-robin; vertices were ordered by decreasing degree once per graph, so
-// every wavefront receives a similar mix.  Changed and scanned counts are
-// kept per wavefront and added to the global counters once at the end.
+// Work decomposition (fixed once per graph by the degree binning):
+//   * a "unit" is a run of at most S consecutive CSR entries of one vertex;
+//     vertices of degree <= S are one unit, vertices above S ("hubs") are
+//     split into ceil(deg / S) segment units;
+//   * one lane owns one unit and feeds its entries into a register sketch in
+//     CSR order, so no sketch merging is needed below S;
+//   * a wavefront takes 64 units at a time (units are ordered by decreasing
+//     length, so its lanes finish together) and stages T entries of each of
+//     its 64 rows through LDS per step: the column, weight and gathered label
+//     loads are issued row-contiguous by the whole wavefront, then every
+//     lane consumes its own row from LDS;
+//   * LPA_MODE_ASYNC: segment sketches are written out as partial sketches
+//     and merged per hub by k_hub_merge (Section 4.3, partial sketches);
+//     labels and flags are updated in place;
+//   * LPA_MODE_DET: vertices above S are scanned by one wavefront each, which
+//     stages 64 entries at a time and feeds them one by one into a sketch
+//     held one slot per lane, so every sketch sees its row in CSR order;
+//     labels are double-buffered (Jacobi).
+//
+// The CSR arrays are streamed once per iteration with non-temporal loads so
+// that they do not evict the label lines that the gathers reuse.
 //
 // Sketch step (Section 4.1, with the decrement reading used throughout the
 // library): a pair (c, w) adds w to the slot holding c; otherwise it fills a
@@ -16,13 +31,7 @@
 // holds c gives the same multiset of live (label, weight) pairs as placing
 // (c, w) in any free slot, and keys stay unique because a key is only
 // written when c is in no slot.  A weight of 0 leaves the sketch unchanged,
-// which is how self-loops are skipped without a branch.
-//
-// LPA_MODE_DET: every sketch is fed in CSR order; labels are read from C and
-// every binned vertex writes its label for the next iteration into Cn
-// (Jacobi, double-buffered labels).
-// LPA_MODE_ASYNC: labels and flags are updated in place; a hub is scanned
-// by 64 lanes with one partial sketch each, merged pairwise (Section 4.3).
+// which is how self-loops and padding are skipped without a branch.
 #include "lpa_internal.h"
 
 #include <limits.h>
@@ -34,14 +43,11 @@ __device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlan
 __device__ __forceinline__ float rfl_f(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
-__device__ __forceinline__ unsigned long long rfl_u64(unsigned long long x) {
-  unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
-  unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x >> 32));
-  return ((unsigned long long)hi << 32) | lo;
-}
-__device__ __forceinline__ int lanes_below(unsigned long long m) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+// Order LDS accesses of this wavefront: the wavefront executes its LDS
+// instructions in order, this only keeps the compiler from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 // ---------------------------------------------------------------------------
@@ -100,6 +106,12 @@ struct LaneSketch {
     }
     return bk;
   }
+
+  // Feed another sketch's live slots (merge of partial sketches).
+  __device__ __forceinline__ void merge_from(const int *pk, const float *pv) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) add(pk[s], pv[s] > 0.0f ? pv[s] : 0.0f);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -151,53 +163,88 @@ __device__ __forceinline__ int wave_max_key(int key, float val, int lane, int ke
 }
 
 // ---------------------------------------------------------------------------
-// Lane path: one lane per vertex, CSR order (exact for LPA_MODE_DET).
+// LDS staging of 64 rows, T entries per row per step.
 // ---------------------------------------------------------------------------
-template <int K, bool ASYNC>
-__device__ __forceinline__ void lane_vertex(const MoveArgs &a, int v, unsigned long long &scanned,
-                                            unsigned long long &changed) {
-  bool active = false;
-  int beg = 0, end = 0, cv = 0;
-  if (v >= 0) {
-    active = a.act_cur[v] != 0;
-    cv = a.C[v];
-    if (active) {
-      a.act_cur[v] = 0;
-      beg = a.row_ptr[v];
-      end = a.row_ptr[v + 1];
-    }
-  }
-  LaneSketch<K> S;
-  S.clear();
-  if (a.w) {
-    for (int e = beg; e < end; ++e) {
-      const int j = a.col[e];
-      const float x = a.w[e];
-      S.add(a.C[j], j == v ? 0.0f : x);
-    }
-  } else {
-    for (int e = beg; e < end; ++e) {
-      const int j = a.col[e];
-      S.add(a.C[j], j == v ? 0.0f : 1.0f);
-    }
-  }
-  const int c = S.max_key(cv);
-  const bool moved = active && c != cv && (!a.pickless || c < cv);
-  if (ASYNC) {
-    if (moved) a.C[v] = c;
-  } else if (v >= 0) {
-    a.Cn[v] = moved ? c : cv;
-  }
-  changed += (unsigned long long)__popcll(__ballot(moved));
-  if (moved)
-    for (int e = beg; e < end; ++e) a.act_next[a.col[e]] = 1;
-  if (active) scanned += (unsigned long long)(end - beg);
+template <int T>
+struct Stage {
+  int beg[kWave];
+  int len[kWave];
+  int self[kWave];
+  int lab[kWave * (T + 1)];
+  float w[kWave * (T + 1)];
+};
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off));
+  return x;
 }
 
+// Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
+// nothing).  All lanes of the wavefront must call it together.
+template <int K, int T>
+__device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T> &st, int lane, int beg,
+                                            int len, int self, LaneSketch<K> &S) {
+  st.beg[lane] = beg;
+  st.len[lane] = len;
+  st.self[lane] = self;
+  const int maxlen = rfl(wave_max(len));
+  wave_lds_sync();
+  for (int t0 = 0; t0 < maxlen; t0 += T) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      const int slot = i * kWave + lane;
+      const int r = slot / T, j = slot % T;
+      const int p = t0 + j;
+      int lab = -1;
+      float x = 0.0f;
+      if (p < st.len[r]) {
+        const int e = st.beg[r] + p;
+        const int c = __builtin_nontemporal_load(a.col + e);
+        x = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
+        if (c == st.self[r]) x = 0.0f;
+        lab = a.C[c];
+      }
+      st.lab[r * (T + 1) + j] = lab;
+      st.w[r * (T + 1) + j] = x;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < T; ++j) S.add(st.lab[lane * (T + 1) + j], st.w[lane * (T + 1) + j]);
+    wave_lds_sync();
+  }
+}
+
+// Flag a neighbour of a changed vertex as unprocessed (plain byte store:
+// reading the flag first to skip repeated marks measured slower).
+__device__ __forceinline__ void mark(const MoveArgs &a, int j) { a.act_next[j] = 1; }
+
+// Mark the neighbours of every lane whose `moved` is set (entries [beg, beg +
+// len) of its row), with row-contiguous column loads by the whole wavefront.
+template <int T>
+__device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T> &st, int lane, int beg,
+                                            int len, bool moved) {
+  if (__ballot(moved) == 0ull) return;
+  st.beg[lane] = beg;
+  st.len[lane] = moved ? len : 0;
+  const int maxlen = rfl(wave_max(moved ? len : 0));
+  wave_lds_sync();
+  for (int t0 = 0; t0 < maxlen; t0 += T) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      const int slot = i * kWave + lane;
+      const int r = slot / T, j = slot % T;
+      const int p = t0 + j;
+      if (p < st.len[r]) mark(a, __builtin_nontemporal_load(a.col + st.beg[r] + p));
+    }
+  }
+  wave_lds_sync();
+}
+
+constexpr int kStageT = 16;
+
 // ---------------------------------------------------------------------------
-// Hub path, LPA_MODE_DET: one wavefront per vertex.  The 64 lanes load and
-// gather 64 consecutive neighbours at a time; the sketch then consumes them
-// one by one in CSR order.
+// LPA_MODE_DET hub path: one wavefront per vertex, CSR order.
 // ---------------------------------------------------------------------------
 template <int K>
 __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &scanned,
@@ -243,81 +290,89 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
   if (lane == 0) a.Cn[v] = moved ? c : cv;
   if (moved) {
     changed += 1;
-    for (int q = beg + lane; q < end; q += kWave) a.act_next[a.col[q]] = 1;
+    for (int q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
   }
   scanned += (unsigned long long)(end - beg);
 }
 
 // ---------------------------------------------------------------------------
-// Hub path, LPA_MODE_ASYNC: lane l keeps a partial sketch of neighbours
-// beg + l, beg + l + 64, ...; the 64 partial sketches are merged by feeding
-// the partner's live slots into one's own (Section 4.3), six times.
-// ---------------------------------------------------------------------------
-template <int K>
-__device__ void hub_vertex_async(const MoveArgs &a, int v, unsigned long long &scanned,
-                                 unsigned long long &changed) {
-  const int lane = threadIdx.x & (kWave - 1);
-  if (a.act_cur[v] == 0) return;
-  if (lane == 0) a.act_cur[v] = 0;
-  const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
-  const int cv = a.C[v];
-  LaneSketch<K> S;
-  S.clear();
-  if (a.w) {
-    for (int e = beg + lane; e < end; e += kWave) {
-      const int j = a.col[e];
-      const float x = a.w[e];
-      S.add(a.C[j], j == v ? 0.0f : x);
-    }
-  } else {
-    for (int e = beg + lane; e < end; e += kWave) {
-      const int j = a.col[e];
-      S.add(a.C[j], j == v ? 0.0f : 1.0f);
-    }
-  }
-#pragma unroll 1
-  for (int off = kWave / 2; off >= 1; off >>= 1) {
-    int pk[K];
-    float pv[K];
-#pragma unroll
-    for (int s = 0; s < K; ++s) {  // snapshot the partner before merging
-      pk[s] = __shfl_xor(S.key[s], off);
-      pv[s] = __shfl_xor(S.val[s], off);
-    }
-#pragma unroll
-    for (int s = 0; s < K; ++s) S.add(pk[s], pv[s] > 0.0f ? pv[s] : 0.0f);
-  }
-  const int c = rfl(S.max_key(cv));
-  const bool moved = c != cv && (!a.pickless || c < cv);
-  if (moved) {
-    if (lane == 0) a.C[v] = c;
-    changed += 1;
-    for (int q = beg + lane; q < end; q += kWave) a.act_next[a.col[q]] = 1;
-  }
-  scanned += (unsigned long long)(end - beg);
-}
-
+// Lane units (both modes).  Unit u < n_seg is segment u - hub_pbase[h] of
+// hub h = seg_hub[u] (async only); otherwise whole vertex order[n_hubs + u -
+// n_seg].
 // ---------------------------------------------------------------------------
 template <int K, bool ASYNC>
+__device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st, int u,
+                                           unsigned long long &scanned,
+                                           unsigned long long &changed) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int v = -1, beg = 0, len = 0, cv = 0, pslot = -1;
+  bool whole = false, active = false;
+  if (ASYNC && u < a.n_seg) {
+    const int h = a.seg_hub[u];
+    v = a.order[h];
+    active = a.hub_act[h] != 0;
+    const int q = u - a.hub_pbase[h];
+    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
+    beg = rb + q * a.seg_len;
+    len = min(a.seg_len, re - beg);
+    pslot = u;
+  } else if (u < a.n_seg + a.n_lane) {
+    v = a.order[a.n_hubs + (u - a.n_seg)];
+    whole = true;
+    active = a.act_cur[v] != 0;
+    cv = a.C[v];
+    if (active) {
+      a.act_cur[v] = 0;
+      beg = a.row_ptr[v];
+      len = a.row_ptr[v + 1] - beg;
+    }
+  }
+  if (!active) len = 0;
+  LaneSketch<K> S;
+  S.clear();
+  staged_scan<K, kStageT>(a, st, lane, beg, len, v, S);
+  scanned += (unsigned long long)len;
+  bool moved = false;
+  if (pslot >= 0) {
+    if (active) {  // partial sketch of one hub segment
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        a.part_key[(size_t)pslot * K + s] = S.key[s];
+        a.part_val[(size_t)pslot * K + s] = S.val[s];
+      }
+    }
+  } else if (whole) {
+    const int c = S.max_key(cv);
+    moved = active && c != cv && (!a.pickless || c < cv);
+    if (ASYNC) {
+      if (moved) a.C[v] = c;
+    } else {
+      a.Cn[v] = moved ? c : cv;
+    }
+  }
+  // every lane reaches here: the marking pass is wavefront-cooperative
+  changed += (unsigned long long)__popcll(__ballot(moved));
+  staged_mark<kStageT>(a, st, lane, beg, len, moved);
+}
+
+template <int K, bool ASYNC>
 __global__ __launch_bounds__(kBlock) void k_move(MoveArgs a) {
+  __shared__ Stage<kStageT> stage[kBlock / kWave];
   if (*a.done) return;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int wib = threadIdx.x / kWave;
+  const int wave = blockIdx.x * (kBlock / kWave) + wib;
   const int nwaves = gridDim.x * (kBlock / kWave);
-  // per-wavefront totals: hub counts are uniform, lane counts are summed
-  // over the wavefront before they are added
   unsigned long long scanned_lane = 0, changed_w = 0, scanned_w = 0;
-  for (int item = wave; item < a.total_items; item += nwaves) {
-    if (item < a.n_hubs) {
-      const int v = a.order[item];
-      if (ASYNC)
-        hub_vertex_async<K>(a, v, scanned_w, changed_w);
-      else
-        hub_vertex_det<K>(a, v, scanned_w, changed_w);
+  const int hub_items = ASYNC ? 0 : a.n_hubs;
+  const int units = (ASYNC ? a.n_seg : 0) + a.n_lane;
+  const int items = hub_items + (units + kWave - 1) / kWave;
+  for (int item = wave; item < items; item += nwaves) {
+    if (item < hub_items) {
+      hub_vertex_det<K>(a, a.order[item], scanned_w, changed_w);
     } else {
-      const int idx = (item - a.n_hubs) * kWave + lane;
-      const int v = idx < a.n_lane ? a.order[a.n_hubs + idx] : -1;
-      lane_vertex<K, ASYNC>(a, v, scanned_lane, changed_w);
+      const int u = (item - hub_items) * kWave + lane;
+      lane_units<K, ASYNC>(a, stage[wib], u, scanned_lane, changed_w);
     }
   }
 #pragma unroll
@@ -329,9 +384,117 @@ __global__ __launch_bounds__(kBlock) void k_move(MoveArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// LPA_MODE_ASYNC hub epilogue.
+// ---------------------------------------------------------------------------
+// Snapshot and clear the unprocessed flags of the hubs before the move
+// kernel, so that marks made while their segments are scanned are kept for
+// the next iteration.
+__global__ void k_hub_snapshot(MoveArgs a) {
+  if (*a.done) return;
+  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < a.n_hubs; h += gridDim.x * blockDim.x) {
+    const int v = a.order[h];
+    a.hub_act[h] = a.act_cur[v];
+    a.act_cur[v] = 0;
+  }
+}
+
+// Merge the partial sketches of every active hub (Section 4.3) and update
+// its label.  A wavefront takes 64 hubs: hubs with at most 64 partials are
+// merged by one lane each; larger ones by the whole wavefront (lane l merges
+// partials l, l + 64, ..., then a pairwise exchange across lanes).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hub_merge(MoveArgs a) {
+  if (*a.done) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int nwaves = gridDim.x * (kBlock / kWave);
+  unsigned long long changed_w = 0;
+  const int items = (a.n_hubs + kWave - 1) / kWave;
+  for (int item = wave; item < items; item += nwaves) {
+    const int h = item * kWave + lane;
+    int v = -1, p0 = 0, np = 0, cv = 0;
+    bool active = false;
+    if (h < a.n_hubs) {
+      v = a.order[h];
+      active = a.hub_act[h] != 0;
+      p0 = a.hub_pbase[h];
+      np = a.hub_pbase[h + 1] - p0;
+      cv = a.C[v];
+    }
+    int c = cv;
+    const bool small = active && np <= kWave;
+    LaneSketch<K> S;
+    S.clear();
+    if (small) {
+      for (int p = p0; p < p0 + np; ++p) {
+        int pk[K];
+        float pv[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+          pk[s] = a.part_key[(size_t)p * K + s];
+          pv[s] = a.part_val[(size_t)p * K + s];
+        }
+        S.merge_from(pk, pv);
+      }
+      c = S.max_key(cv);
+    }
+    unsigned long long big = __ballot(active && !small);
+    while (big) {
+      const int src = __ffsll((long long)big) - 1;
+      big &= big - 1;
+      const int bp0 = __shfl(p0, src), bnp = __shfl(np, src), bcv = __shfl(cv, src);
+      LaneSketch<K> B;
+      B.clear();
+      for (int p = bp0 + lane; p < bp0 + bnp; p += kWave) {
+        int pk[K];
+        float pv[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+          pk[s] = a.part_key[(size_t)p * K + s];
+          pv[s] = a.part_val[(size_t)p * K + s];
+        }
+        B.merge_from(pk, pv);
+      }
+#pragma unroll 1
+      for (int off = kWave / 2; off >= 1; off >>= 1) {
+        int pk[K];
+        float pv[K];
+#pragma unroll
+        for (int s = 0; s < K; ++s) {  // snapshot the partner before merging
+          pk[s] = __shfl_xor(B.key[s], off);
+          pv[s] = __shfl_xor(B.val[s], off);
+        }
+        B.merge_from(pk, pv);
+      }
+      const int bc = rfl(B.max_key(bcv));
+      if (lane == src) c = bc;
+    }
+    const bool moved = active && c != cv && (!a.pickless || c < cv);
+    if (moved) a.C[v] = c;
+    const unsigned long long mv = __ballot(moved);
+    changed_w += (unsigned long long)__popcll(mv);
+    unsigned long long rest = mv;
+    while (rest) {  // every moved hub marks its neighbours, row-contiguous
+      const int src = __ffsll((long long)rest) - 1;
+      rest &= rest - 1;
+      const int bv = __shfl(v, src);
+      const int rb = a.row_ptr[bv], re = a.row_ptr[bv + 1];
+      for (int e = rb + lane; e < re; e += kWave) mark(a, __builtin_nontemporal_load(a.col + e));
+    }
+  }
+  if (lane == 0 && changed_w) atomicAdd(a.dN + a.iter, changed_w);
+}
+
+// ---------------------------------------------------------------------------
 template <int K, bool ASYNC>
-static hipError_t launch_t(const MoveArgs &a, int grid, hipStream_t s) {
+static hipError_t launch_t(const MoveArgs &a, int grid, int merge_grid, hipStream_t s) {
+  if (ASYNC && a.n_hubs > 0)
+    hipLaunchKernelGGL(k_hub_snapshot, dim3((a.n_hubs + 255) / 256 < 1024 ? (a.n_hubs + 255) / 256 : 1024),
+                       dim3(256), 0, s, a);
   hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, a);
+  if (ASYNC && a.n_hubs > 0)
+    hipLaunchKernelGGL((k_hub_merge<K>), dim3(merge_grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -345,14 +508,14 @@ static int occ_t() {
 }
 
 template <bool ASYNC>
-static hipError_t launch_mode(int k, const MoveArgs &a, int grid, hipStream_t s) {
+static hipError_t launch_mode(int k, const MoveArgs &a, int grid, int merge_grid, hipStream_t s) {
   switch (k) {
-    case 1: return launch_t<1, ASYNC>(a, grid, s);
-    case 2: return launch_t<2, ASYNC>(a, grid, s);
-    case 4: return launch_t<4, ASYNC>(a, grid, s);
-    case 8: return launch_t<8, ASYNC>(a, grid, s);
-    case 16: return launch_t<16, ASYNC>(a, grid, s);
-    case 32: return launch_t<32, ASYNC>(a, grid, s);
+    case 1: return launch_t<1, ASYNC>(a, grid, merge_grid, s);
+    case 2: return launch_t<2, ASYNC>(a, grid, merge_grid, s);
+    case 4: return launch_t<4, ASYNC>(a, grid, merge_grid, s);
+    case 8: return launch_t<8, ASYNC>(a, grid, merge_grid, s);
+    case 16: return launch_t<16, ASYNC>(a, grid, merge_grid, s);
+    case 32: return launch_t<32, ASYNC>(a, grid, merge_grid, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -370,8 +533,10 @@ static int occ_mode(int k) {
   }
 }
 
-hipError_t launch_move(int k, bool async_mode, const MoveArgs &a, int grid, hipStream_t s) {
-  return async_mode ? launch_mode<true>(k, a, grid, s) : launch_mode<false>(k, a, grid, s);
+hipError_t launch_move(int k, bool async_mode, const MoveArgs &a, int grid, int merge_grid,
+                       hipStream_t s) {
+  return async_mode ? launch_mode<true>(k, a, grid, merge_grid, s)
+                    : launch_mode<false>(k, a, grid, merge_grid, s);
 }
 
 int move_blocks_per_cu(int k, bool async_mode) {
