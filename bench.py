@@ -40,8 +40,10 @@ def log(msg):
 
 
 def traffic_from_profiles(kernel: str, workload: str, src_digest: str):
-    """HBM bytes per launch measured with rocprofv3 counters, if a summary in
-    profiles/ matches this kernel, workload and source digest."""
+    """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counters (each scaled by the same counter's reading for a
+    device copy of known size), if a summary in profiles/ was taken on this
+    kernel source, kernel and workload; else None."""
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -135,7 +137,22 @@ def main():
     ap.add_argument("--lane-max-degree", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy // 4
+        src = torch.arange(n, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "launches": 3}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -201,6 +218,7 @@ def main():
     elapsed = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps in {elapsed:.3f}s; iterations {iters}")
 
+    floor_ms = solver.memory_floor_ms(3)
     labels = solver.labels(device=True)
     tq = time.perf_counter()
     q = solver.modularity()
@@ -210,7 +228,8 @@ def main():
 
     achieved = kernel_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
     digest = source_digest()
-    traffic = traffic_from_profiles(f"k_move<{args.k},{str(args.mode == 'async').lower()}>",
+    kname = f"lpa::k_move<{args.k}, {'true' if args.mode == 'async' else 'false'}>"
+    traffic = traffic_from_profiles(kname,
                                     workload, digest)
     result = {
         "metric": METRIC,
@@ -231,10 +250,17 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic,
-                     "kernel": f"k_move<{args.k},{str(args.mode == 'async').lower()}>",
+                     "kernel": kname,
                      "bytes_per_edge": BYTES_PER_EDGE, "launches": launches,
                      "avg_launch_ms": round(kernel_ms / max(launches, 1), 4),
                      "source_digest": digest},
+        "scan_memory_floor": {
+            "ms": round(floor_ms, 4),
+            "GBps": round(BYTES_PER_EDGE * g.nnz / (floor_ms * 1e-3) / 1e9, 1) if floor_ms > 0 else None,
+            "what": "stream col+w and gather every neighbour label once, no sketch (lpa_memory_floor)",
+            "kernel_frac_of_floor": round((BYTES_PER_EDGE * g.nnz / (floor_ms * 1e-3) / 1e9) and
+                                          achieved / (BYTES_PER_EDGE * g.nnz / (floor_ms * 1e-3) / 1e9), 4)
+            if floor_ms > 0 else None},
         "iterations": iters[-1],
         "iter0": {"scanned": int(sc[0]) if len(sc) else 0,
                   "move_ms": round(float(ms[0]), 4) if len(ms) else None,

@@ -175,8 +175,10 @@ int lpa_set_state(lpa_handle *h, const int32_t *labels,
 int lpa_memory(const lpa_handle *h, size_t *core_bytes, size_t *eval_bytes);
 
 /* Kernel timing: when enabled, HIP events are recorded on the handle's
- * stream immediately before and after the move kernel (the neighbourhood
- * scan, sketch and label update) of every iteration.  Enabling it creates
+ * stream immediately before and after the move kernel k_move (the
+ * neighbourhood scans, sketches and label updates; in LPA_MODE_ASYNC the
+ * hub flag snapshot before it and the hub merge after it are outside) of
+ * every iteration.  Enabling it creates
  * the events; it is off by default. */
 int lpa_profile(lpa_handle *h, int enable);
 
@@ -184,6 +186,14 @@ int lpa_profile(lpa_handle *h, int enable);
  * current run (move_ms[i] for i < *count = iterations run; at most
  * capacity written).  LPA_ERR_STATE when profiling is off.  Synchronises. */
 int lpa_get_profile(lpa_handle *h, float *move_ms, int capacity, int *count);
+
+/* Memory-pattern floor of one full scan of this graph: time (ms, best of
+ * `reps` >= 1 launches) of a kernel that performs only the scan's memory
+ * accesses (streams col_idx and the weights, gathers the label of every
+ * neighbour) and none of the sketch work.  It bounds from below what the
+ * move kernel can reach on this graph and GPU.  Does not change any state;
+ * synchronises. */
+int lpa_memory_floor(lpa_handle *h, int reps, float *ms);
 
 /* Release the handle and its device memory (synchronises its stream first).
  * NULL is accepted. */

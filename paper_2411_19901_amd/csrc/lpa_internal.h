@@ -53,8 +53,11 @@ struct MoveArgs {
   const int32_t *done;
 };
 
+// Enqueue one iteration's move pass (async: hub flag snapshot, k_move, hub
+// merge; det: k_move).  Non-null events are recorded around k_move only.
 hipError_t launch_move(int k, bool async_mode, const MoveArgs &a, int grid,
-                       int merge_grid, hipStream_t s);
+                       int merge_grid, hipStream_t s, hipEvent_t ev_beg,
+                       hipEvent_t ev_end);
 int move_blocks_per_cu(int k, bool async_mode);
 
 }  // namespace lpa

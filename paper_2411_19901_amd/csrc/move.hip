@@ -488,11 +488,15 @@ __global__ __launch_bounds__(kBlock) void k_hub_merge(MoveArgs a) {
 
 // ---------------------------------------------------------------------------
 template <int K, bool ASYNC>
-static hipError_t launch_t(const MoveArgs &a, int grid, int merge_grid, hipStream_t s) {
+static hipError_t launch_t(const MoveArgs &a, int grid, int merge_grid, hipStream_t s,
+                           hipEvent_t ev_beg, hipEvent_t ev_end) {
+  hipError_t e = hipSuccess;
   if (ASYNC && a.n_hubs > 0)
     hipLaunchKernelGGL(k_hub_snapshot, dim3((a.n_hubs + 255) / 256 < 1024 ? (a.n_hubs + 255) / 256 : 1024),
                        dim3(256), 0, s, a);
+  if (ev_beg && (e = hipEventRecord(ev_beg, s)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, a);
+  if (ev_end && (e = hipEventRecord(ev_end, s)) != hipSuccess) return e;
   if (ASYNC && a.n_hubs > 0)
     hipLaunchKernelGGL((k_hub_merge<K>), dim3(merge_grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
@@ -508,14 +512,15 @@ static int occ_t() {
 }
 
 template <bool ASYNC>
-static hipError_t launch_mode(int k, const MoveArgs &a, int grid, int merge_grid, hipStream_t s) {
+static hipError_t launch_mode(int k, const MoveArgs &a, int grid, int merge_grid, hipStream_t s,
+                              hipEvent_t b, hipEvent_t e) {
   switch (k) {
-    case 1: return launch_t<1, ASYNC>(a, grid, merge_grid, s);
-    case 2: return launch_t<2, ASYNC>(a, grid, merge_grid, s);
-    case 4: return launch_t<4, ASYNC>(a, grid, merge_grid, s);
-    case 8: return launch_t<8, ASYNC>(a, grid, merge_grid, s);
-    case 16: return launch_t<16, ASYNC>(a, grid, merge_grid, s);
-    case 32: return launch_t<32, ASYNC>(a, grid, merge_grid, s);
+    case 1: return launch_t<1, ASYNC>(a, grid, merge_grid, s, b, e);
+    case 2: return launch_t<2, ASYNC>(a, grid, merge_grid, s, b, e);
+    case 4: return launch_t<4, ASYNC>(a, grid, merge_grid, s, b, e);
+    case 8: return launch_t<8, ASYNC>(a, grid, merge_grid, s, b, e);
+    case 16: return launch_t<16, ASYNC>(a, grid, merge_grid, s, b, e);
+    case 32: return launch_t<32, ASYNC>(a, grid, merge_grid, s, b, e);
     default: return hipErrorInvalidValue;
   }
 }
@@ -534,9 +539,9 @@ static int occ_mode(int k) {
 }
 
 hipError_t launch_move(int k, bool async_mode, const MoveArgs &a, int grid, int merge_grid,
-                       hipStream_t s) {
-  return async_mode ? launch_mode<true>(k, a, grid, merge_grid, s)
-                    : launch_mode<false>(k, a, grid, merge_grid, s);
+                       hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
+  return async_mode ? launch_mode<true>(k, a, grid, merge_grid, s, ev_beg, ev_end)
+                    : launch_mode<false>(k, a, grid, merge_grid, s, ev_beg, ev_end);
 }
 
 int move_blocks_per_cu(int k, bool async_mode) {

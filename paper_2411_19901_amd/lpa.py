@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
                                          ctypes.c_int]),
         "lpa_memory": (ctypes.c_int, [H, szp, szp]),
         "lpa_profile": (ctypes.c_int, [H, ctypes.c_int]),
+        "lpa_memory_floor": (ctypes.c_int, [H, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
         "lpa_get_profile": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_float), ctypes.c_int, ip]),
         "lpa_free": (ctypes.c_int, [H]),
         "lpa_error_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -207,6 +208,12 @@ def lpa_get_profile(h, capacity: int) -> np.ndarray:
     return ms[:min(cnt.value, capacity)].copy()
 
 
+def lpa_memory_floor(h, reps: int = 3) -> float:
+    ms = ctypes.c_float(0.0)
+    _check(load().lpa_memory_floor(h, reps, ctypes.byref(ms)), "lpa_memory_floor", h)
+    return float(ms.value)
+
+
 def lpa_free(h) -> None:
     if h:
         load().lpa_free(h)
@@ -291,6 +298,9 @@ class LPA:
 
     def move_ms(self) -> np.ndarray:
         return lpa_get_profile(self.h, self.max_iter)
+
+    def memory_floor_ms(self, reps: int = 3) -> float:
+        return lpa_memory_floor(self.h, reps)
 
     def memory(self) -> Tuple[int, int]:
         return lpa_memory(self.h)
