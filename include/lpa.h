@@ -92,15 +92,21 @@ typedef struct lpa_config {
                               vertex, higher degrees cooperatively;
                               0 = default for the mode.  Never changes
                               LPA_MODE_DET results. */
-  int32_t check_every;     /* lpa_run reads the convergence flag on the host
-                              every this many iterations and stops launching
-                              once it is set; 0 = enqueue all max_iter
-                              iterations (finished ones exit on the device)
-                              and synchronise once */
-  int32_t reserved[6];     /* must be zero */
+  int32_t check_every;     /* lpa_run / lpa_batch_run read the convergence
+                              state on the host every this many iterations
+                              and stop launching once every graph finished;
+                              0 = enqueue all remaining iterations (finished
+                              graphs exit on the device), synchronise once */
+  void *workspace;         /* optional device memory for every array of the
+                              handle (256-byte aligned, at least
+                              lpa_workspace_bytes); NULL = lpa_init allocates
+                              one block itself.  Borrowed like the graph. */
+  size_t workspace_bytes;
+  int32_t reserved[4];     /* must be zero */
 } lpa_config;
 
 typedef struct lpa_handle lpa_handle;
+typedef struct lpa_batch lpa_batch;
 
 /* Fill *cfg with the defaults (det mode, rho 8, null stream, validation on). */
 void lpa_config_default(lpa_config *cfg);
@@ -120,6 +126,12 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol,
              int max_iter, uint64_t seed, const lpa_config *cfg,
              lpa_handle **out);
 
+/* Device bytes lpa_init needs for a graph of n vertices and nnz entries
+ * with these parameters (cfg NULL = defaults); the size of a caller
+ * workspace (lpa_config.workspace). */
+int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter,
+                        const lpa_config *cfg, size_t *bytes);
+
 /* Return the handle to iteration 0 (labels = ids, all vertices unprocessed,
  * traces cleared) without re-binning.  Enqueued; does not synchronise. */
 int lpa_reset(lpa_handle *h);
@@ -134,6 +146,35 @@ int lpa_step(lpa_handle *h, int64_t *changed, int *done);
 /* Run iterations until convergence or max_iter, then synchronise.
  * *iterations (may be NULL) = total iterations run since init / reset. */
 int lpa_run(lpa_handle *h, int *iterations);
+
+/* Batched launches.  A batch runs iterations of many handles (one graph
+ * each) with one set of kernel launches per iteration: every graph keeps its
+ * own iteration count, pick-less schedule, pruning flags, counters and
+ * convergence test, so each handle ends exactly as lpa_run would leave it
+ * (bit-identical labels in LPA_MODE_DET).  The handles passed to one call
+ * must share k, mode, device and stream with the batch, appear once, and
+ * number at most `capacity`; the set may change between calls (continuous
+ * batching).  The batch owns only its launch tables.
+ *   cfg: mode flags, stream and check_every are used (NULL = defaults). */
+int lpa_batch_create(int capacity, int k, const lpa_config *cfg, lpa_batch **out);
+
+/* One iteration of every unfinished handle in hs[0..count); synchronises.
+ * *changed = sum of their dN; *all_done = 1 when every handle has finished.
+ * Either output may be NULL. */
+int lpa_batch_step(lpa_batch *b, lpa_handle *const *hs, int count, int64_t *changed,
+                   int *all_done);
+
+/* Iterate every handle in hs[0..count) until each has converged or reached
+ * max_iter; synchronises.  *iterations = the largest iteration count. */
+int lpa_batch_run(lpa_batch *b, lpa_handle *const *hs, int count, int *iterations);
+
+/* Release the batch (not its handles).  NULL is accepted. */
+int lpa_batch_free(lpa_batch *b);
+
+/* Progress of h as of its last synchronising call (no device access):
+ * *iteration = iterations run, *finished = 1 once converged or at max_iter.
+ * Either pointer may be NULL. */
+int lpa_progress(const lpa_handle *h, int *iteration, int *finished);
 
 /* Modularity Q of Eq. 1, community-sum form, accumulated in fp64.
  * labels: device int32[n] with values in [0, n), or NULL for the handle's

@@ -172,26 +172,21 @@ __global__ void k_fill_seg_hub(const int32_t *pbase, int n_hubs, int32_t *seg_hu
     for (int q = pbase[h]; q < pbase[h + 1]; ++q) seg_hub[q] = h;
 }
 
-// ctl[0] = done, ctl[1] = iterations run
-__global__ void k_finish(const unsigned long long *dN, int iter, int n, double tol, int rho,
-                         int max_iter, int *ctl) {
-  if (threadIdx.x != 0 || ctl[0]) return;
-  const bool pl = rho > 0 && iter % rho == 0;
-  ctl[1] = iter + 1;
-  const double frac = (double)dN[iter] / (double)n;
-  if ((!pl && frac < tol) || iter + 1 >= max_iter) ctl[0] = 1;
-}
-
-__global__ void k_clear_err(int *ctl) {
-  if (threadIdx.x == 0) ctl[2] = 0;
-}
-
-__global__ void k_set_ctl(int *ctl, int done, int iters) {
+__global__ void k_status_set(GraphStatus *st, int iter, int done) {
   if (threadIdx.x == 0) {
-    ctl[0] = done;
-    ctl[1] = iters;
-    ctl[2] = 0;
+    st->iter = iter;
+    st->done = done;
+    st->err = 0;
   }
+}
+
+__global__ void k_status_clear_err(GraphStatus *st) {
+  if (threadIdx.x == 0) st->err = 0;
+}
+
+__global__ void k_zero_i32(int32_t *p, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 // --- modularity (Eq. 1, community-sum form), fp64 --------------------------
@@ -304,8 +299,35 @@ int grid_for(size_t count, int block = kAuxBlock, int cap = 4096) {
 }  // namespace
 
 // ===========================================================================
-// Handle
+// Handles and batches
 // ===========================================================================
+struct lpa_batch {
+  int capacity = 0;
+  int k = 8;
+  bool async_mode = false;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int check_every = 0;
+  int cus = 1;
+  int grid_cap = 1;  // resident k_move workgroups
+  void *dblock = nullptr;  // device: descriptors, prefixes, finished counter, status
+  GraphDesc *d_desc = nullptr;
+  int32_t *d_prefix = nullptr;  // items[cap+1], hubs[cap+1], merge[cap+1]
+  int32_t *d_finished = nullptr;
+  int32_t *d_status = nullptr;  // [2 * cap]
+  void *hblock = nullptr;  // pinned host mirror of the same layout
+  GraphDesc *h_desc = nullptr;
+  int32_t *h_prefix = nullptr;
+  int32_t *h_finished = nullptr;
+  int32_t *h_status = nullptr;
+  size_t block_bytes = 0;
+  size_t off_prefix = 0, off_finished = 0, off_status = 0;
+  std::vector<lpa_handle *> loaded;
+  int total_items = 0, total_hubs = 0, total_merge = 0, unfinished = 0;
+  bool poisoned = false;
+  std::string err;
+};
+
 struct lpa_handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -323,32 +345,24 @@ struct lpa_handle {
   uint64_t seed = 0;
   int lane_max = 0;
   int check_every = 0;
-  std::vector<hipEvent_t> ev_beg, ev_end;  // per-iteration move timing
 
-  int32_t *C[2] = {nullptr, nullptr};    // det: labels of even / odd iterations; async: C[0]
-  uint8_t *act[2] = {nullptr, nullptr};   // det: flags of even / odd iterations; async: act[0]
-  int32_t *order = nullptr;
-  int32_t *hub_pbase = nullptr;  // async: [n_hubs + 1]
-  int32_t *seg_hub = nullptr;    // async: [n_seg]
-  uint8_t *hub_act = nullptr;    // async: [n_hubs]
-  int32_t *part_key = nullptr;   // async: [n_seg * k]
-  float *part_val = nullptr;     // async: [n_seg * k]
-  int n_seg = 0;
-  int grid_merge = 1;
-  unsigned long long *dN = nullptr;       // [max(1, max_iter)]
-  unsigned long long *scanned = nullptr;  // [max(1, max_iter)]
-  int *ctl = nullptr;                     // [0] done, [1] iterations, [2] error bits, [3..] totals
+  void *block = nullptr;  // every device array of the handle
+  bool owns_block = false;
+  GraphDesc desc{};       // host copy of the static descriptor
+  GraphStatus *st = nullptr;
+  uint32_t *hist = nullptr;  // binning scratch
+  int32_t seg_cap = 0, hub_cap = 0;
   double *mod_tot = nullptr;
   double *mod_acc = nullptr;
+  std::vector<void *> eval_allocs;
 
-  int n_hubs = 0, n_lane = 0;
-  int grid_move = 1;
-  int iter = 0;  // next iteration index (host view)
+  int iter = 0;  // iterations run (host mirror of st->iter)
   bool finished = false;
   size_t core_bytes = 0, eval_bytes = 0;
   bool poisoned = false;
   std::string err;
-  std::vector<void *> allocs;
+  std::vector<hipEvent_t> ev_beg, ev_end;
+  lpa_batch *self = nullptr;  // batch of one used by lpa_step / lpa_run
 };
 
 namespace {
@@ -366,40 +380,33 @@ int fail_hip(lpa_handle *h, hipError_t e, const char *what) {
   return LPA_ERR_HIP;
 }
 
-#define HIP_TRY(h, expr)                                 \
-  do {                                                   \
-    hipError_t _e = (expr);                              \
+int fail_hip_b(lpa_batch *b, hipError_t e, const char *what) {
+  if (b) {
+    b->poisoned = true;
+    b->err = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return LPA_ERR_HIP;
+}
+
+#define HIP_TRY(h, expr)                                   \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
     if (_e != hipSuccess) return fail_hip((h), _e, #expr); \
   } while (0)
 
-#define LAUNCH_TRY(h, what)                              \
-  do {                                                   \
-    hipError_t _e = hipGetLastError();                   \
-    if (_e != hipSuccess) return fail_hip((h), _e, what); \
+#define LAUNCH_TRY(h, what)                                \
+  do {                                                     \
+    hipError_t _e = hipGetLastError();                     \
+    if (_e != hipSuccess) return fail_hip((h), _e, what);  \
   } while (0)
 
-template <typename T>
-int dev_alloc(lpa_handle *h, T **p, size_t count, bool core = true) {
-  void *q = nullptr;
-  const size_t bytes = (count ? count : 1) * sizeof(T);
-  hipError_t e = hipMalloc(&q, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return set_err(h, LPA_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  }
-  h->allocs.push_back(q);
-  if (core)
-    h->core_bytes += bytes;
-  else
-    h->eval_bytes += bytes;
-  *p = (T *)q;
-  return LPA_OK;
-}
+#define HIP_TRY_B(b, expr)                                   \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return fail_hip_b((b), _e, #expr); \
+  } while (0)
 
 bool k_supported(int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32; }
-
-// labels after the iterations run so far
-int32_t *cur_labels(const lpa_handle *h) { return h->async_mode ? h->C[0] : h->C[h->iter & 1]; }
 
 int check_ready(lpa_handle *h) {
   if (!h) return LPA_ERR_ARG;
@@ -410,84 +417,246 @@ int check_ready(lpa_handle *h) {
 // Longest run of CSR entries one lane scans (measured on R-MAT scale 24).
 int default_lane_max(bool async_mode) { return async_mode ? 2048 : 1024; }
 
-// Enqueue iteration state for iteration 0.
+// labels after the iterations run so far
+int32_t *cur_labels(const lpa_handle *h) { return h->desc.C[h->iter & 1]; }
+uint8_t *cur_flags(const lpa_handle *h) { return h->desc.act[h->iter & 1]; }
+
+// --- one device block per handle -------------------------------------------
+struct Layout {
+  size_t st, dN, scanned, C0, C1, act0, act1, order, hist, hub_pbase, hub_act, seg_hub, pkey,
+      pval, total;
+  int32_t hub_cap, seg_cap, ncls;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode, int lane_max) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + (bytes ? bytes : 1));
+    return at;
+  };
+  const size_t T = (size_t)(max_iter > 0 ? max_iter : 1);
+  L.ncls = kHubClasses + lane_max + 1;
+  L.st = take(sizeof(GraphStatus));
+  L.dN = take(T * 8);
+  L.scanned = take(T * 8);
+  L.C0 = take((size_t)n * 4);
+  L.C1 = async_mode ? L.C0 : take((size_t)n * 4);
+  L.act0 = take((size_t)n);
+  L.act1 = async_mode ? L.act0 : take((size_t)n);
+  L.order = take((size_t)n * 4);
+  L.hist = take((size_t)L.ncls * 4);
+  if (async_mode) {
+    // hubs have more than S entries each; a hub of degree d > S has
+    // ceil(d / S) < 2 d / S segments
+    const int64_t hubs = nnz / (lane_max + 1) + 1;
+    L.hub_cap = (int32_t)(hubs < n ? hubs : n);
+    L.seg_cap = (int32_t)(2 * nnz / lane_max + 1);
+    L.hub_pbase = take(((size_t)L.hub_cap + 1) * 4);
+    L.hub_act = take((size_t)L.hub_cap);
+    L.seg_hub = take((size_t)L.seg_cap * 4);
+    L.pkey = take((size_t)L.seg_cap * k * 4);
+    L.pval = take((size_t)L.seg_cap * k * 4);
+  }
+  L.total = off;
+  return L;
+}
+
+// Enqueue iteration-0 state.
 int enqueue_reset(lpa_handle *h) {
   const int n = h->n;
   const size_t T = (size_t)(h->max_iter > 0 ? h->max_iter : 1);
   if (n > 0) {
-    hipLaunchKernelGGL(k_fill_i32_iota, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->C[0], n);
-    if (h->C[1])
-      hipLaunchKernelGGL(k_fill_i32_iota, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->C[1],
-                         n);
-    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->act[0],
+    hipLaunchKernelGGL(k_fill_i32_iota, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                       h->desc.C[0], n);
+    if (h->desc.C[1] != h->desc.C[0])
+      hipLaunchKernelGGL(k_fill_i32_iota, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                         h->desc.C[1], n);
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->desc.act[0],
                        (size_t)n, (uint8_t)1);
-    if (h->act[1])
-      hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->act[1],
-                         (size_t)n, (uint8_t)0);
+    if (h->desc.act[1] != h->desc.act[0])
+      hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                         h->desc.act[1], (size_t)n, (uint8_t)0);
   }
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(T)), dim3(kAuxBlock), 0, h->stream, h->dN, T);
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(T)), dim3(kAuxBlock), 0, h->stream, h->scanned, T);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(T)), dim3(kAuxBlock), 0, h->stream, h->desc.dN, T);
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(T)), dim3(kAuxBlock), 0, h->stream,
+                     h->desc.scanned, T);
   const bool done0 = (n == 0 || h->max_iter == 0);
-  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, h->stream, h->ctl, done0 ? 1 : 0, 0);
+  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, 0, done0 ? 1 : 0);
   LAUNCH_TRY(h, "reset kernels");
   h->iter = 0;
   h->finished = done0;
   return LPA_OK;
 }
 
-// Enqueue iteration l (move, apply, convergence test).
-int enqueue_iteration(lpa_handle *h, int l) {
-  MoveArgs a;
-  a.n = h->n;
-  a.row_ptr = h->row_ptr;
-  a.col = h->col;
-  a.w = h->w;
-  if (h->async_mode) {
-    a.C = a.Cn = h->C[0];
-    a.act_cur = a.act_next = h->act[0];
-  } else {
-    a.C = h->C[l & 1];
-    a.Cn = h->C[(l + 1) & 1];
-    a.act_cur = h->act[l & 1];
-    a.act_next = h->act[(l + 1) & 1];
+// --- batches -----------------------------------------------------------------
+int batch_alloc(lpa_batch *b) {
+  const size_t cap = (size_t)b->capacity;
+  size_t off = 0;
+  off = align_up(cap * sizeof(GraphDesc));
+  b->off_prefix = off;
+  off = align_up(off + 3 * (cap + 1) * sizeof(int32_t));
+  b->off_finished = off;
+  off = align_up(off + sizeof(int32_t));
+  b->off_status = off;
+  off = align_up(off + 2 * cap * sizeof(int32_t));
+  b->block_bytes = off;
+  if (hipMalloc(&b->dblock, off) != hipSuccess) {
+    (void)hipGetLastError();
+    return LPA_ERR_NOMEM;
   }
-  a.order = h->order;
-  a.n_hubs = h->n_hubs;
-  a.n_lane = h->n_lane;
-  a.seg_len = h->lane_max;
-  a.n_seg = h->async_mode ? h->n_seg : 0;
-  a.seg_hub = h->seg_hub;
-  a.hub_pbase = h->hub_pbase;
-  a.hub_act = h->hub_act;
-  a.part_key = h->part_key;
-  a.part_val = h->part_val;
-  a.iter = l;
-  a.pickless = (h->rho > 0 && l % h->rho == 0) ? 1 : 0;
-  a.dN = h->dN;
-  a.scanned = h->scanned;
-  a.done = h->ctl;
-  const bool prof = !h->ev_beg.empty();
-  hipEvent_t eb = prof ? h->ev_beg[l] : nullptr, ee = prof ? h->ev_end[l] : nullptr;
-  if (h->n_hubs + h->n_lane > 0) {
-    hipError_t e = launch_move(h->k, h->async_mode, a, h->grid_move, h->grid_merge, h->stream, eb, ee);
-    if (e != hipSuccess) return fail_hip(h, e, "move kernel launch");
-  } else if (prof) {
-    HIP_TRY(h, hipEventRecord(eb, h->stream));
-    HIP_TRY(h, hipEventRecord(ee, h->stream));
+  if (hipHostMalloc(&b->hblock, off, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return LPA_ERR_NOMEM;
   }
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, h->stream, (const unsigned long long *)h->dN,
-                     l, h->n, h->tol, h->rho, h->max_iter, h->ctl);
-  LAUNCH_TRY(h, "iteration kernels");
+  char *d = (char *)b->dblock, *hh = (char *)b->hblock;
+  b->d_desc = (GraphDesc *)d;
+  b->h_desc = (GraphDesc *)hh;
+  b->d_prefix = (int32_t *)(d + b->off_prefix);
+  b->h_prefix = (int32_t *)(hh + b->off_prefix);
+  b->d_finished = (int32_t *)(d + b->off_finished);
+  b->h_finished = (int32_t *)(hh + b->off_finished);
+  b->d_status = (int32_t *)(d + b->off_status);
+  b->h_status = (int32_t *)(hh + b->off_status);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LPA_ERR_HIP;
+  b->device = dev;
+  if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return LPA_ERR_HIP;
+  b->grid_cap = b->cus * move_blocks_per_cu(b->k, b->async_mode);
   return LPA_OK;
 }
 
-int read_ctl(lpa_handle *h, int *done, int *iters) {
-  int host[2] = {0, 0};
-  HIP_TRY(h, hipMemcpyAsync(host, h->ctl, sizeof(host), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipStreamSynchronize(h->stream));
-  *done = host[0];
-  *iters = host[1];
+void batch_release(lpa_batch *b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->dblock) (void)hipFree(b->dblock);
+  if (b->hblock) (void)hipHostFree(b->hblock);
+  delete b;
+}
+
+int move_items(const lpa_handle *h) { return h->desc.items; }
+
+// Upload the descriptor table for hs[0..count).
+int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
+  if (count < 0 || count > b->capacity) return LPA_ERR_ARG;
+  int32_t *pi = b->h_prefix, *ph = b->h_prefix + (b->capacity + 1),
+          *pm = b->h_prefix + 2 * (b->capacity + 1);
+  pi[0] = ph[0] = pm[0] = 0;
+  int unfinished = 0;
+  for (int g = 0; g < count; ++g) {
+    lpa_handle *h = hs[g];
+    if (!h) return LPA_ERR_ARG;
+    if (h->poisoned) return LPA_ERR_HIP;
+    if (h->k != b->k || h->async_mode != b->async_mode || h->device != b->device ||
+        h->stream != b->stream)
+      return LPA_ERR_ARG;
+    for (int q = 0; q < g; ++q)
+      if (hs[q] == h) return LPA_ERR_ARG;
+    b->h_desc[g] = h->desc;
+    const bool live = !h->finished;
+    unfinished += live ? 1 : 0;
+    pi[g + 1] = pi[g] + (live ? move_items(h) : 0);
+    ph[g + 1] = ph[g] + (live && b->async_mode ? h->desc.n_hubs : 0);
+    pm[g + 1] = pm[g] + (live && b->async_mode ? (h->desc.n_hubs + kWave - 1) / kWave : 0);
+  }
+  // pad the prefixes to the table capacity so the three arrays keep their offsets
+  b->total_items = pi[count];
+  b->total_hubs = ph[count];
+  b->total_merge = pm[count];
+  b->unfinished = unfinished;
+  b->loaded.assign(hs, hs + count);
+  HIP_TRY_B(b, hipMemcpyAsync(b->d_desc, b->h_desc, (size_t)count * sizeof(GraphDesc),
+                              hipMemcpyHostToDevice, b->stream));
+  HIP_TRY_B(b, hipMemcpyAsync(b->d_prefix, b->h_prefix, 3 * (b->capacity + 1) * sizeof(int32_t),
+                              hipMemcpyHostToDevice, b->stream));
   return LPA_OK;
+}
+
+Launch make_launch(lpa_batch *b) {
+  Launch L;
+  L.d = b->d_desc;
+  L.prefix_items = b->d_prefix;
+  L.prefix_hubs = b->d_prefix + (b->capacity + 1);
+  L.prefix_merge = b->d_prefix + 2 * (b->capacity + 1);
+  L.G = (int32_t)b->loaded.size();
+  L.total_items = b->total_items;
+  L.total_hubs = b->total_hubs;
+  L.total_merge = b->total_merge;
+  L.finished = b->d_finished;
+  L.status_out = b->d_status;
+  return L;
+}
+
+// Read the status of every loaded graph back into the handles.
+int batch_read_status(lpa_batch *b) {
+  const int G = (int)b->loaded.size();
+  if (G > 0)
+    HIP_TRY_B(b, hipMemcpyAsync(b->h_status, b->d_status, 2 * (size_t)G * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY_B(b, hipMemcpyAsync(b->h_finished, b->d_finished, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              b->stream));
+  HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+  for (int g = 0; g < G; ++g) {
+    lpa_handle *h = b->loaded[g];
+    if (h->finished) continue;
+    h->iter = b->h_status[2 * g];
+    h->finished = b->h_status[2 * g + 1] != 0;
+  }
+  return LPA_OK;
+}
+
+// Run up to `iters` iterations of the loaded graphs; poll every check_every.
+// prof: handle whose per-iteration events are recorded (single-graph runs).
+int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
+  if (b->unfinished == 0 || iters <= 0) return LPA_OK;
+  const Launch L = make_launch(b);
+  const int waves_per_block = kBlock / kWave;
+  int grid = (b->total_items + waves_per_block - 1) / waves_per_block;
+  if (grid > b->grid_cap) grid = b->grid_cap;
+  if (grid < 1) grid = 1;
+  int mg = (b->total_merge + waves_per_block - 1) / waves_per_block;
+  if (mg > b->cus * 4) mg = b->cus * 4;
+  if (mg < 1) mg = 1;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->stream, b->d_finished, 1);
+  for (int i = 0; i < iters; ++i) {
+    hipEvent_t eb = nullptr, ee = nullptr;
+    if (prof && !prof->ev_beg.empty()) {
+      const int l = prof->iter + i;
+      if (l < (int)prof->ev_beg.size()) {
+        eb = prof->ev_beg[l];
+        ee = prof->ev_end[l];
+      }
+    }
+    hipError_t e = launch_iteration(b->k, b->async_mode, L, grid, mg, b->stream, eb, ee);
+    if (e != hipSuccess) return fail_hip_b(b, e, "iteration launch");
+    if (b->check_every > 0 && (i + 1) % b->check_every == 0 && i + 1 < iters) {
+      HIP_TRY_B(b, hipMemcpyAsync(b->h_finished, b->d_finished, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY_B(b, hipStreamSynchronize(b->stream));
+      if (*b->h_finished >= b->unfinished) break;
+    }
+  }
+  return LPA_OK;
+}
+
+int batch_error_to_handles(lpa_batch *b, int rc) {
+  if (rc == LPA_ERR_HIP)
+    for (lpa_handle *h : b->loaded) {
+      h->poisoned = true;
+      h->err = b->err;
+    }
+  return rc;
+}
+
+int max_remaining(lpa_batch *b) {
+  int m = 0;
+  for (lpa_handle *h : b->loaded)
+    if (!h->finished && h->max_iter - h->iter > m) m = h->max_iter - h->iter;
+  return m;
 }
 
 }  // namespace
@@ -510,7 +679,7 @@ const char *lpa_error_string(int code) {
     case LPA_ERR_ARG: return "invalid argument";
     case LPA_ERR_GRAPH: return "invalid graph, weights or labels";
     case LPA_ERR_UNSUPPORTED: return "unsupported parameter (k or mode)";
-    case LPA_ERR_NOMEM: return "device allocation failed";
+    case LPA_ERR_NOMEM: return "device allocation failed or workspace too small";
     case LPA_ERR_HIP: return "HIP runtime error (handle poisoned)";
     case LPA_ERR_STATE: return "handle in the wrong state for this call";
     default: return "unknown status";
@@ -519,12 +688,45 @@ const char *lpa_error_string(int code) {
 
 const char *lpa_last_error(const lpa_handle *h) { return h ? h->err.c_str() : ""; }
 
+static int check_config(const lpa_config &cfg) {
+  for (int i = 0; i < 4; ++i)
+    if (cfg.reserved[i] != 0) return LPA_ERR_ARG;
+  if (cfg.rho < 0 || cfg.lane_max_degree < 0 || cfg.lane_max_degree > 65536 ||
+      cfg.check_every < 0)
+    return LPA_ERR_ARG;
+  const uint32_t mode = cfg.flags & LPA_MODE_MASK;
+  if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
+  if ((cfg.flags & ~(LPA_MODE_MASK | LPA_VALIDATE)) != 0) return LPA_ERR_UNSUPPORTED;
+  if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
+  return LPA_OK;
+}
+
+int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter, const lpa_config *cfg_in,
+                        size_t *bytes) {
+  if (!bytes) return LPA_ERR_ARG;
+  lpa_config cfg;
+  if (cfg_in)
+    cfg = *cfg_in;
+  else
+    lpa_config_default(&cfg);
+  if (n < 0 || nnz < 0 || nnz >= (int64_t)INT32_MAX || max_iter < 0) return LPA_ERR_ARG;
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
+  const bool async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
+  const int lane_max = cfg.lane_max_degree > 0 ? cfg.lane_max_degree : default_lane_max(async_mode);
+  *bytes = plan_layout(n, nnz, k, max_iter, async_mode, lane_max).total;
+  return LPA_OK;
+}
+
 int lpa_free(lpa_handle *h) {
   if (!h) return LPA_OK;
   (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev_beg) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_end) (void)hipEventDestroy(e);
-  for (void *p : h->allocs) (void)hipFree(p);
+  for (void *p : h->eval_allocs) (void)hipFree(p);
+  if (h->owns_block && h->block) (void)hipFree(h->block);
+  batch_release(h->self);
   delete h;
   return LPA_OK;
 }
@@ -539,18 +741,13 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     cfg = *cfg_in;
   else
     lpa_config_default(&cfg);
-  for (int i = 0; i < 6; ++i)
-    if (cfg.reserved[i] != 0) return LPA_ERR_ARG;
-  if (cfg.check_every < 0) return LPA_ERR_ARG;
+  int rc = check_config(cfg);
+  if (rc) return rc;
   if (g->n < 0 || g->n == INT32_MAX || g->nnz < 0 || g->nnz >= (int64_t)INT32_MAX) return LPA_ERR_ARG;
   if (g->n > 0 && !g->row_ptr) return LPA_ERR_ARG;
   if (g->nnz > 0 && !g->col_idx) return LPA_ERR_ARG;
   if (g->n == 0 && g->nnz != 0) return LPA_ERR_ARG;
-  if (!(tol >= 0.0 && tol <= 1.0) || max_iter < 0 || cfg.rho < 0 || cfg.lane_max_degree < 0)
-    return LPA_ERR_ARG;
-  const uint32_t mode = cfg.flags & LPA_MODE_MASK;
-  if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
-  if ((cfg.flags & ~(LPA_MODE_MASK | LPA_VALIDATE)) != 0) return LPA_ERR_UNSUPPORTED;
+  if (!(tol >= 0.0 && tol <= 1.0) || max_iter < 0) return LPA_ERR_ARG;
   if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
 
   lpa_handle *h = new (std::nothrow) lpa_handle();
@@ -566,42 +763,70 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   h->max_iter = max_iter;
   h->rho = cfg.rho;
   h->flags = cfg.flags;
-  h->async_mode = (mode == LPA_MODE_ASYNC);
+  h->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   h->seed = seed;
   h->check_every = cfg.check_every;
   h->lane_max = cfg.lane_max_degree > 0 ? cfg.lane_max_degree : default_lane_max(h->async_mode);
-  if (h->lane_max > 4096) h->lane_max = 4096;
-
-  int rc = LPA_OK;
   auto bail = [&](int code) {
-    std::string msg = h->err;
     lpa_free(h);
-    (void)msg;
     return code;
   };
   if (hipGetDevice(&h->device) != hipSuccess) return bail(LPA_ERR_HIP);
 
+  // one block for every array of the handle: the caller's workspace or ours
   const int n = h->n;
-  const size_t T = (size_t)(max_iter > 0 ? max_iter : 1);
-  if ((rc = dev_alloc(h, &h->C[0], (size_t)n)) != LPA_OK) return bail(rc);
-  if ((rc = dev_alloc(h, &h->act[0], (size_t)n)) != LPA_OK) return bail(rc);
-  if (!h->async_mode) {
-    if ((rc = dev_alloc(h, &h->C[1], (size_t)n)) != LPA_OK) return bail(rc);
-    if ((rc = dev_alloc(h, &h->act[1], (size_t)n)) != LPA_OK) return bail(rc);
+  const Layout Ly = plan_layout(n, h->nnz, k, max_iter, h->async_mode, h->lane_max);
+  if (cfg.workspace) {
+    if (cfg.workspace_bytes < Ly.total || ((uintptr_t)cfg.workspace & 255) != 0)
+      return bail(LPA_ERR_NOMEM);
+    h->block = cfg.workspace;
+  } else {
+    if (hipMalloc(&h->block, Ly.total) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(set_err(h, LPA_ERR_NOMEM, "hipMalloc failed"));
+    }
+    h->owns_block = true;
   }
-  if ((rc = dev_alloc(h, &h->order, (size_t)n)) != LPA_OK) return bail(rc);
-  if ((rc = dev_alloc(h, &h->dN, T)) != LPA_OK) return bail(rc);
-  if ((rc = dev_alloc(h, &h->scanned, T)) != LPA_OK) return bail(rc);
-  if ((rc = dev_alloc(h, &h->ctl, 8)) != LPA_OK) return bail(rc);
+  h->core_bytes = Ly.total;
+  char *base = (char *)h->block;
+  h->st = (GraphStatus *)(base + Ly.st);
+  h->hist = (uint32_t *)(base + Ly.hist);
+  GraphDesc &d = h->desc;
+  d.n = n;
+  d.seg_len = h->lane_max;
+  d.max_iter = max_iter;
+  d.rho = h->rho;
+  d.tol = tol;
+  d.row_ptr = h->row_ptr;
+  d.col = h->col;
+  d.w = h->w;
+  d.C[0] = (int32_t *)(base + Ly.C0);
+  d.C[1] = (int32_t *)(base + Ly.C1);
+  d.act[0] = (uint8_t *)(base + Ly.act0);
+  d.act[1] = (uint8_t *)(base + Ly.act1);
+  d.order = (const int32_t *)(base + Ly.order);
+  d.dN = (unsigned long long *)(base + Ly.dN);
+  d.scanned = (unsigned long long *)(base + Ly.scanned);
+  d.st = h->st;
+  if (h->async_mode) {
+    h->hub_cap = Ly.hub_cap;
+    h->seg_cap = Ly.seg_cap;
+    d.hub_pbase = (const int32_t *)(base + Ly.hub_pbase);
+    d.hub_act = (uint8_t *)(base + Ly.hub_act);
+    d.seg_hub = (const int32_t *)(base + Ly.seg_hub);
+    d.part_key = (int32_t *)(base + Ly.pkey);
+    d.part_val = (float *)(base + Ly.pval);
+  }
 
-  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, h->stream, h->ctl, 0, 0);
+  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, 0, 0);
+  if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
   if (n > 0 && (cfg.flags & LPA_VALIDATE)) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(h->nnz > n ? (size_t)h->nnz : (size_t)n)),
                        dim3(kAuxBlock), 0, h->stream, n, h->nnz, h->row_ptr, h->col, h->w,
-                       h->ctl + 2);
+                       &h->st->err);
     int bad = 0;
     if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&bad, h->ctl + 2, sizeof(int), hipMemcpyDeviceToHost, h->stream) !=
+        hipMemcpyAsync(&bad, &h->st->err, sizeof(int), hipMemcpyDeviceToHost, h->stream) !=
             hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
       return bail(LPA_ERR_HIP);
@@ -610,68 +835,56 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
 
   // degree binning (once per graph)
   if (n > 0) {
-    const int ncls = kHubClasses + h->lane_max + 1;
-    unsigned *hist = nullptr;
-    if (hipMalloc(&hist, ncls * sizeof(unsigned)) != hipSuccess) return bail(LPA_ERR_NOMEM);
-    bool ok = hipMemsetAsync(hist, 0, ncls * sizeof(unsigned), h->stream) == hipSuccess;
-    if (ok) {
-      hipLaunchKernelGGL(k_bin_hist, dim3(grid_for(n, kAuxBlock, 2048)), dim3(kAuxBlock),
-                         ncls * sizeof(unsigned), h->stream, n, h->row_ptr, h->lane_max, ncls,
-                         hist);
-      hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(64), 0, h->stream, ncls, hist, h->ctl + 3);
-      const int per_block = kAuxBlock * kScatterItems;
-      hipLaunchKernelGGL(k_bin_scatter, dim3((n + per_block - 1) / per_block), dim3(kAuxBlock),
-                         2 * ncls * sizeof(unsigned), h->stream, n, h->row_ptr, h->lane_max, ncls,
-                         hist, h->order);
-      ok = hipGetLastError() == hipSuccess;
-    }
-    int totals[2] = {0, 0};
-    if (ok)
-      ok = hipMemcpyAsync(totals, h->ctl + 3, sizeof(totals), hipMemcpyDeviceToHost, h->stream) ==
-               hipSuccess &&
-           hipStreamSynchronize(h->stream) == hipSuccess;
-    (void)hipFree(hist);
-    if (!ok) return bail(LPA_ERR_HIP);
-    h->n_hubs = totals[0];
-    h->n_lane = totals[1];
-  }
-
-  // async: split every hub into segments of lane_max entries
-  if (h->async_mode && h->n_hubs > 0) {
-    if ((rc = dev_alloc(h, &h->hub_pbase, (size_t)h->n_hubs + 1)) != LPA_OK) return bail(rc);
-    if ((rc = dev_alloc(h, &h->hub_act, (size_t)h->n_hubs)) != LPA_OK) return bail(rc);
-    hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(1024), 0, h->stream, (const int32_t *)h->order,
-                       h->n_hubs, h->row_ptr, h->lane_max, h->hub_pbase, h->ctl + 5);
-    int nseg = 0;
+    const int ncls = Ly.ncls;
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(ncls)), dim3(kAuxBlock), 0, h->stream,
+                       (int32_t *)h->hist, ncls);
+    hipLaunchKernelGGL(k_bin_hist, dim3(grid_for(n, kAuxBlock, 2048)), dim3(kAuxBlock),
+                       ncls * sizeof(unsigned), h->stream, n, h->row_ptr, h->lane_max, ncls,
+                       (unsigned *)h->hist);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(64), 0, h->stream, ncls, (unsigned *)h->hist,
+                       h->st->totals);
+    const int per_block = kAuxBlock * kScatterItems;
+    hipLaunchKernelGGL(k_bin_scatter, dim3((n + per_block - 1) / per_block), dim3(kAuxBlock),
+                       2 * ncls * sizeof(unsigned), h->stream, n, h->row_ptr, h->lane_max, ncls,
+                       (unsigned *)h->hist, (int32_t *)d.order);
+    int totals[4] = {0, 0, 0, 0};
     if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&nseg, h->ctl + 5, sizeof(int), hipMemcpyDeviceToHost, h->stream) !=
+        hipMemcpyAsync(totals, h->st->totals, sizeof(totals), hipMemcpyDeviceToHost, h->stream) !=
             hipSuccess ||
         hipStreamSynchronize(h->stream) != hipSuccess)
       return bail(LPA_ERR_HIP);
-    h->n_seg = nseg;
-    if ((rc = dev_alloc(h, &h->seg_hub, (size_t)nseg)) != LPA_OK) return bail(rc);
-    if ((rc = dev_alloc(h, &h->part_key, (size_t)nseg * k)) != LPA_OK) return bail(rc);
-    if ((rc = dev_alloc(h, &h->part_val, (size_t)nseg * k)) != LPA_OK) return bail(rc);
-    hipLaunchKernelGGL(k_fill_seg_hub, dim3(grid_for(h->n_hubs)), dim3(kAuxBlock), 0, h->stream,
-                       (const int32_t *)h->hub_pbase, h->n_hubs, h->seg_hub);
+    d.n_hubs = totals[0];
+    d.n_lane = totals[1];
+  }
+  // async: split every hub into segments of lane_max entries
+  if (h->async_mode && d.n_hubs > 0) {
+    if (d.n_hubs > h->hub_cap) return bail(set_err(h, LPA_ERR_GRAPH, "hub bound violated"));
+    hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(1024), 0, h->stream, d.order, d.n_hubs,
+                       h->row_ptr, h->lane_max, (int32_t *)d.hub_pbase, &h->st->totals[2]);
+    int nseg = 0;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&nseg, &h->st->totals[2], sizeof(int), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return bail(LPA_ERR_HIP);
+    if (nseg > h->seg_cap) return bail(set_err(h, LPA_ERR_GRAPH, "segment bound violated"));
+    d.n_seg = nseg;
+    hipLaunchKernelGGL(k_fill_seg_hub, dim3(grid_for(d.n_hubs)), dim3(kAuxBlock), 0, h->stream,
+                       d.hub_pbase, d.n_hubs, (int32_t *)d.seg_hub);
     if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
   }
+  d.items = h->async_mode ? (d.n_seg + d.n_lane + kWave - 1) / kWave
+                          : d.n_hubs + (d.n_lane + kWave - 1) / kWave;
 
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
-    return bail(LPA_ERR_HIP);
-  const int waves_per_block = kBlock / kWave;
-  int grid = cus * move_blocks_per_cu(k, h->async_mode);
-  const int units = (h->async_mode ? h->n_seg : 0) + h->n_lane;
-  const int items = (h->async_mode ? 0 : h->n_hubs) + (units + kWave - 1) / kWave;
-  const int need = (items + waves_per_block - 1) / waves_per_block;
-  if (grid > need) grid = need;
-  h->grid_move = grid > 0 ? grid : 1;
-  const int merge_items = (h->n_hubs + kWave - 1) / kWave;
-  int mg = (merge_items + waves_per_block - 1) / waves_per_block;
-  if (mg > cus * 4) mg = cus * 4;
-  h->grid_merge = mg > 0 ? mg : 1;
-
+  // the batch of one that lpa_step / lpa_run use
+  h->self = new (std::nothrow) lpa_batch();
+  if (!h->self) return bail(LPA_ERR_NOMEM);
+  h->self->capacity = 1;
+  h->self->k = k;
+  h->self->async_mode = h->async_mode;
+  h->self->stream = h->stream;
+  h->self->check_every = h->check_every;
+  if ((rc = batch_alloc(h->self)) != LPA_OK) return bail(rc);
   if ((rc = enqueue_reset(h)) != LPA_OK) return bail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LPA_ERR_HIP);
   *out = h;
@@ -693,14 +906,14 @@ int lpa_step(lpa_handle *h, int64_t *changed, int *done) {
     return LPA_OK;
   }
   const int l = h->iter;
-  if ((rc = enqueue_iteration(h, l)) != LPA_OK) return rc;
-  unsigned long long d = 0;
-  HIP_TRY(h, hipMemcpyAsync(&d, h->dN + l, sizeof(d), hipMemcpyDeviceToHost, h->stream));
-  int dn = 0, it = 0;
-  if ((rc = read_ctl(h, &dn, &it)) != LPA_OK) return rc;
-  h->iter = l + 1;
-  h->finished = dn != 0;
-  if (changed) *changed = (int64_t)d;
+  lpa_batch *b = h->self;
+  lpa_handle *one[1] = {h};
+  if ((rc = batch_load(b, one, 1)) != LPA_OK) return batch_error_to_handles(b, rc);
+  if ((rc = batch_iterate(b, 1, h)) != LPA_OK) return batch_error_to_handles(b, rc);
+  unsigned long long dn = 0;
+  HIP_TRY(h, hipMemcpyAsync(&dn, h->desc.dN + l, sizeof(dn), hipMemcpyDeviceToHost, h->stream));
+  if ((rc = batch_read_status(b)) != LPA_OK) return batch_error_to_handles(b, rc);
+  if (changed) *changed = (int64_t)dn;
   if (done) *done = h->finished ? 1 : 0;
   return LPA_OK;
 }
@@ -709,19 +922,85 @@ int lpa_run(lpa_handle *h, int *iterations) {
   int rc = check_ready(h);
   if (rc) return rc;
   if (!h->finished) {
-    int dn = 0, it = 0;
-    for (int l = h->iter; l < h->max_iter; ++l) {
-      if ((rc = enqueue_iteration(h, l)) != LPA_OK) return rc;
-      if (h->check_every > 0 && (l + 1 - h->iter) % h->check_every == 0 && l + 1 < h->max_iter) {
-        if ((rc = read_ctl(h, &dn, &it)) != LPA_OK) return rc;
-        if (dn) break;
-      }
-    }
-    if ((rc = read_ctl(h, &dn, &it)) != LPA_OK) return rc;
-    h->iter = it > h->iter ? it : h->iter;
-    h->finished = true;
+    lpa_batch *b = h->self;
+    lpa_handle *one[1] = {h};
+    if ((rc = batch_load(b, one, 1)) != LPA_OK) return batch_error_to_handles(b, rc);
+    if ((rc = batch_iterate(b, h->max_iter - h->iter, h)) != LPA_OK)
+      return batch_error_to_handles(b, rc);
+    if ((rc = batch_read_status(b)) != LPA_OK) return batch_error_to_handles(b, rc);
   }
   if (iterations) *iterations = h->iter;
+  return LPA_OK;
+}
+
+int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **out) {
+  if (!out) return LPA_ERR_ARG;
+  *out = nullptr;
+  if (capacity < 1 || capacity > (1 << 24)) return LPA_ERR_ARG;
+  lpa_config cfg;
+  if (cfg_in)
+    cfg = *cfg_in;
+  else
+    lpa_config_default(&cfg);
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
+  lpa_batch *b = new (std::nothrow) lpa_batch();
+  if (!b) return LPA_ERR_NOMEM;
+  b->capacity = capacity;
+  b->k = k;
+  b->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
+  b->stream = (hipStream_t)cfg.stream;
+  b->check_every = cfg.check_every;
+  if ((rc = batch_alloc(b)) != LPA_OK) {
+    batch_release(b);
+    return rc;
+  }
+  *out = b;
+  return LPA_OK;
+}
+
+int lpa_batch_free(lpa_batch *b) {
+  batch_release(b);
+  return LPA_OK;
+}
+
+int lpa_batch_step(lpa_batch *b, lpa_handle *const *hs, int count, int64_t *changed,
+                   int *all_done) {
+  if (!b || (count > 0 && !hs)) return LPA_ERR_ARG;
+  if (b->poisoned) return LPA_ERR_HIP;
+  int rc = batch_load(b, hs, count);
+  if (rc) return batch_error_to_handles(b, rc);
+  std::vector<int> before(count);
+  for (int g = 0; g < count; ++g) before[g] = hs[g]->finished ? -1 : hs[g]->iter;
+  if ((rc = batch_iterate(b, 1, nullptr)) != LPA_OK) return batch_error_to_handles(b, rc);
+  if ((rc = batch_read_status(b)) != LPA_OK) return batch_error_to_handles(b, rc);
+  int64_t total = 0;
+  bool all = true;
+  for (int g = 0; g < count; ++g) {
+    if (before[g] >= 0) {
+      unsigned long long dn = 0;
+      HIP_TRY_B(b, hipMemcpy(&dn, hs[g]->desc.dN + before[g], sizeof(dn), hipMemcpyDeviceToHost));
+      total += (int64_t)dn;
+    }
+    all = all && hs[g]->finished;
+  }
+  if (changed) *changed = total;
+  if (all_done) *all_done = all ? 1 : 0;
+  return LPA_OK;
+}
+
+int lpa_batch_run(lpa_batch *b, lpa_handle *const *hs, int count, int *iterations) {
+  if (!b || (count > 0 && !hs)) return LPA_ERR_ARG;
+  if (b->poisoned) return LPA_ERR_HIP;
+  int rc = batch_load(b, hs, count);
+  if (rc) return batch_error_to_handles(b, rc);
+  if ((rc = batch_iterate(b, max_remaining(b), nullptr)) != LPA_OK)
+    return batch_error_to_handles(b, rc);
+  if ((rc = batch_read_status(b)) != LPA_OK) return batch_error_to_handles(b, rc);
+  int m = 0;
+  for (int g = 0; g < count; ++g) m = hs[g]->iter > m ? hs[g]->iter : m;
+  if (iterations) *iterations = m;
   return LPA_OK;
 }
 
@@ -747,11 +1026,12 @@ int lpa_get_trace(lpa_handle *h, int64_t *changed, int64_t *scanned, int capacit
   if (m > 0) {
     std::vector<unsigned long long> tmp((size_t)m);
     if (changed) {
-      HIP_TRY(h, hipMemcpy(tmp.data(), h->dN, m * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+      HIP_TRY(h, hipMemcpy(tmp.data(), h->desc.dN, m * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost));
       for (int i = 0; i < m; ++i) changed[i] = (int64_t)tmp[i];
     }
     if (scanned) {
-      HIP_TRY(h, hipMemcpy(tmp.data(), h->scanned, m * sizeof(unsigned long long),
+      HIP_TRY(h, hipMemcpy(tmp.data(), h->desc.scanned, m * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost));
       for (int i = 0; i < m; ++i) scanned[i] = (int64_t)tmp[i];
     }
@@ -770,34 +1050,42 @@ int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q) {
     return LPA_OK;
   }
   if (!h->mod_tot) {
-    if ((rc = dev_alloc(h, &h->mod_tot, (size_t)n, false)) != LPA_OK) return rc;
-    if ((rc = dev_alloc(h, &h->mod_acc, 4, false)) != LPA_OK) return rc;
+    void *p = nullptr;
+    if (hipMalloc(&p, align_up((size_t)n * sizeof(double)) + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_err(h, LPA_ERR_NOMEM, "hipMalloc failed");
+    }
+    h->eval_allocs.push_back(p);
+    h->eval_bytes += align_up((size_t)n * sizeof(double)) + 256;
+    h->mod_tot = (double *)p;
+    h->mod_acc = (double *)((char *)p + align_up((size_t)n * sizeof(double)));
     hipLaunchKernelGGL(k_zero_d, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->mod_tot, n);
   }
   const int32_t *lab = labels ? labels : cur_labels(h);
+  const GraphDesc &d = h->desc;
   hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, h->stream, h->mod_acc, 4);
-  hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, h->stream, h->ctl);
-  if (h->n_hubs > 0)
-    hipLaunchKernelGGL(k_mod_hub, dim3(grid_for((size_t)h->n_hubs * 64, kAuxBlock, 2048)),
-                       dim3(kAuxBlock), 0, h->stream, (const int32_t *)h->order, h->n_hubs,
-                       h->row_ptr, h->col, h->w, lab, n, h->mod_tot, h->mod_acc, h->ctl + 2);
-  if (h->n_lane > 0)
-    hipLaunchKernelGGL(k_mod_lane, dim3(grid_for(h->n_lane, kAuxBlock, 4096)), dim3(kAuxBlock), 0,
-                       h->stream, (const int32_t *)h->order, h->n_hubs, h->n_lane, h->row_ptr,
-                       h->col, h->w, lab, n, h->mod_tot, h->mod_acc, h->ctl + 2);
+  hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
+  if (d.n_hubs > 0)
+    hipLaunchKernelGGL(k_mod_hub, dim3(grid_for((size_t)d.n_hubs * 64, kAuxBlock, 2048)),
+                       dim3(kAuxBlock), 0, h->stream, d.order, d.n_hubs, h->row_ptr, h->col, h->w,
+                       lab, n, h->mod_tot, h->mod_acc, &h->st->err);
+  if (d.n_lane > 0)
+    hipLaunchKernelGGL(k_mod_lane, dim3(grid_for(d.n_lane, kAuxBlock, 4096)), dim3(kAuxBlock), 0,
+                       h->stream, d.order, d.n_hubs, d.n_lane, h->row_ptr, h->col, h->w, lab, n,
+                       h->mod_tot, h->mod_acc, &h->st->err);
   hipLaunchKernelGGL(k_mod_sq, dim3(grid_for(n, kAuxBlock, 4096)), dim3(kAuxBlock), 0, h->stream,
                      h->mod_tot, n, h->mod_acc);
   LAUNCH_TRY(h, "modularity kernels");
   double acc[4] = {0, 0, 0, 0};
   int bad = 0;
   HIP_TRY(h, hipMemcpyAsync(acc, h->mod_acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(&bad, h->ctl + 2, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(&bad, &h->st->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   if (bad) {
-    // labels of vertices with degree 0 are not visited above; out of range
-    // labels among the others were skipped, so tot may hold stale sums
+    // out-of-range labels were skipped, so the per-community totals may be
+    // partial: clear them for the next call
     hipLaunchKernelGGL(k_zero_d, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->mod_tot, n);
-    hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, h->stream, h->ctl);
+    hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
     LAUNCH_TRY(h, "modularity reset");
     return set_err(h, LPA_ERR_GRAPH, "label out of range [0, n)");
   }
@@ -814,10 +1102,8 @@ int lpa_get_state(lpa_handle *h, int32_t *labels, uint8_t *unprocessed, int *ite
   const hipMemcpyKind kind = is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   if (n > 0 && labels)
     HIP_TRY(h, hipMemcpyAsync(labels, cur_labels(h), (size_t)n * sizeof(int32_t), kind, h->stream));
-  if (n > 0 && unprocessed) {
-    const uint8_t *src = h->async_mode ? h->act[0] : h->act[h->iter & 1];
-    HIP_TRY(h, hipMemcpyAsync(unprocessed, src, (size_t)n, kind, h->stream));
-  }
+  if (n > 0 && unprocessed)
+    HIP_TRY(h, hipMemcpyAsync(unprocessed, cur_flags(h), (size_t)n, kind, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   if (iteration) *iteration = h->iter;
   return LPA_OK;
@@ -836,33 +1122,34 @@ int lpa_set_state(lpa_handle *h, const int32_t *labels, const uint8_t *unprocess
         if (labels[i] < 0 || labels[i] >= n)
           return set_err(h, LPA_ERR_GRAPH, "label out of range [0, n)");
     } else {
-      hipLaunchKernelGGL(k_clear_err, dim3(1), dim3(64), 0, h->stream, h->ctl);
+      hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
       hipLaunchKernelGGL(k_check_labels, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, labels,
-                         n, h->ctl + 2);
+                         n, &h->st->err);
       LAUNCH_TRY(h, "label check");
       int bad = 0;
-      HIP_TRY(h, hipMemcpyAsync(&bad, h->ctl + 2, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(&bad, &h->st->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
       HIP_TRY(h, hipStreamSynchronize(h->stream));
       if (bad) return set_err(h, LPA_ERR_GRAPH, "label out of range [0, n)");
     }
   }
   // counters of every iteration start from zero again
   if ((rc = enqueue_reset(h)) != LPA_OK) return rc;
+  const GraphDesc &d = h->desc;
   if (n > 0) {
     const hipMemcpyKind kind = is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    uint8_t *cur = h->async_mode ? h->act[0] : h->act[iteration & 1];
-    HIP_TRY(h, hipMemcpyAsync(h->C[0], labels, (size_t)n * sizeof(int32_t), kind, h->stream));
-    if (h->C[1])  // both buffers: vertices of degree 0 are never rewritten
-      HIP_TRY(h, hipMemcpyAsync(h->C[1], labels, (size_t)n * sizeof(int32_t), kind, h->stream));
+    uint8_t *cur = d.act[iteration & 1];
+    HIP_TRY(h, hipMemcpyAsync(d.C[0], labels, (size_t)n * sizeof(int32_t), kind, h->stream));
+    if (d.C[1] != d.C[0])  // both buffers: vertices of degree 0 are never rewritten
+      HIP_TRY(h, hipMemcpyAsync(d.C[1], labels, (size_t)n * sizeof(int32_t), kind, h->stream));
     HIP_TRY(h, hipMemcpyAsync(cur, unprocessed, (size_t)n, kind, h->stream));
     hipLaunchKernelGGL(k_normalize_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, cur, n);
-    if (!h->async_mode)
+    if (d.act[1] != d.act[0])
       hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
-                         h->act[(iteration + 1) & 1], (size_t)n, (uint8_t)0);
+                         d.act[(iteration + 1) & 1], (size_t)n, (uint8_t)0);
     LAUNCH_TRY(h, "state restore");
   }
   const bool fin = (n == 0 || iteration >= h->max_iter);
-  hipLaunchKernelGGL(k_set_ctl, dim3(1), dim3(64), 0, h->stream, h->ctl, fin ? 1 : 0, iteration);
+  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, iteration, fin ? 1 : 0);
   LAUNCH_TRY(h, "state restore");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   h->iter = iteration;
@@ -916,7 +1203,7 @@ int lpa_memory_floor(lpa_handle *h, int reps, float *ms) {
   for (int r = 0; r < reps + 1; ++r) {  // the first launch warms the caches
     HIP_TRY(h, hipEventRecord(b, h->stream));
     hipLaunchKernelGGL(k_scan_floor, dim3(4096), dim3(kAuxBlock), 0, h->stream, h->col, h->w,
-                       (const int32_t *)cur_labels(h), h->nnz, (unsigned long long *)(h->ctl + 6));
+                       (const int32_t *)cur_labels(h), h->nnz, &h->st->sink);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(e, h->stream));
     HIP_TRY(h, hipEventSynchronize(e));
@@ -927,6 +1214,14 @@ int lpa_memory_floor(lpa_handle *h, int reps, float *ms) {
   (void)hipEventDestroy(b);
   (void)hipEventDestroy(e);
   *ms = best;
+  return LPA_OK;
+}
+
+int lpa_progress(const lpa_handle *h, int *iteration, int *finished) {
+  if (!h) return LPA_ERR_ARG;
+  if (h->poisoned) return LPA_ERR_HIP;
+  if (iteration) *iteration = h->iter;
+  if (finished) *finished = h->finished ? 1 : 0;
   return LPA_OK;
 }
 

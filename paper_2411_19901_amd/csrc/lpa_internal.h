@@ -12,7 +12,7 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;  // threads per workgroup for the move kernels
 
 // Degree classes used to order vertices by decreasing degree.  Classes
-// 0..255 hold hubs (degree > lane_max_degree) on a log scale with eight
+// 0..255 hold hubs (degree > lane_max) on a log scale with eight
 // sub-buckets per octave; classes 256..256+T-1 hold degrees T..1 exactly.
 constexpr int kHubClasses = 256;
 
@@ -25,39 +25,88 @@ __host__ __device__ inline int degree_class(int d, int lane_max) {
   return kHubClasses + (lane_max - d);
 }
 
-// Arguments of one lpaMove launch.
+// Device-resident progress of one graph, updated by the convergence kernel.
+struct GraphStatus {
+  int32_t iter;       // iterations run so far
+  int32_t done;       // converged or max_iter reached
+  int32_t err;        // validation / label-check error bits
+  int32_t totals[4];  // binning results: hubs, lane vertices, segments
+  int32_t pad;
+  unsigned long long sink;
+};
+
+// Static description of one graph's arrays (pointers never change after
+// lpa_init); a launch reads a table of these.
+struct GraphDesc {
+  int32_t n;
+  int32_t n_hubs;     // vertices of degree > seg_len
+  int32_t n_lane;     // vertices of degree 1 .. seg_len
+  int32_t n_seg;      // async hub segments (0 in det mode)
+  int32_t seg_len;    // S: longest run of CSR entries one lane scans
+  int32_t max_iter;
+  int32_t rho;
+  int32_t items;      // move-kernel work items per iteration
+  double tol;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const float *w;     // nullable: unit weights
+  int32_t *C[2];      // det: labels of even / odd iterations; async: both C[0]
+  uint8_t *act[2];    // det: flags of even / odd iterations; async: both act[0]
+  const int32_t *order;      // vertex ids: hubs (desc degree), then lane vertices
+  const int32_t *seg_hub;    // [n_seg] hub index of each segment
+  const int32_t *hub_pbase;  // [n_hubs + 1] first segment of each hub
+  uint8_t *hub_act;          // [n_hubs] flags snapshot of this iteration
+  int32_t *part_key;         // [n_seg * k]
+  float *part_val;           // [n_seg * k]
+  unsigned long long *dN;       // [max_iter] changed vertices per iteration
+  unsigned long long *scanned;  // [max_iter] CSR entries scanned per iteration
+  GraphStatus *st;
+};
+
+// One set of launches over many graphs.  prefix_* hold G + 1 exclusive
+// prefix sums of the per-graph counts (move items, hubs, merge items).
+struct Launch {
+  const GraphDesc *d;
+  const int32_t *prefix_items;
+  const int32_t *prefix_hubs;
+  const int32_t *prefix_merge;
+  int32_t G;
+  int32_t total_items;
+  int32_t total_hubs;
+  int32_t total_merge;
+  int32_t *finished;        // graphs that have finished (counter)
+  int32_t *status_out;      // [2 * G]: iter, done of every graph after the launch
+};
+
+// Per-graph view used by the move kernels for one iteration.
 struct MoveArgs {
   int32_t n;
   const int32_t *row_ptr;
   const int32_t *col;
-  const float *w;          // nullable: unit weights
+  const float *w;
   int32_t *C;              // labels read this iteration (async: read/write)
   int32_t *Cn;             // labels written this iteration (async: == C)
   uint8_t *act_cur;        // unprocessed flags read (and cleared) this iteration
   uint8_t *act_next;       // flags set for the next iteration (async: == act_cur)
-  const int32_t *order;    // vertex ids: hubs (desc degree), then lane vertices
-  int32_t n_hubs;          // vertices of degree > seg_len
-  int32_t n_lane;          // vertices of degree 1 .. seg_len
-  int32_t seg_len;         // S: longest run of CSR entries one lane scans
-  // LPA_MODE_ASYNC hub segments and partial sketches
-  int32_t n_seg;                // segment units (0 in det mode)
-  const int32_t *seg_hub;       // [n_seg] hub index of each segment
-  const int32_t *hub_pbase;     // [n_hubs + 1] first segment of each hub
-  uint8_t *hub_act;             // [n_hubs] flags snapshot of this iteration
-  int32_t *part_key;            // [n_seg * k]
-  float *part_val;              // [n_seg * k]
+  const int32_t *order;
+  int32_t n_hubs;
+  int32_t n_lane;
+  int32_t seg_len;
+  int32_t n_seg;
+  const int32_t *seg_hub;
+  const int32_t *hub_pbase;
+  uint8_t *hub_act;
+  int32_t *part_key;
+  float *part_val;
   int32_t iter;
   int32_t pickless;
-  unsigned long long *dN;       // [max_iter]
-  unsigned long long *scanned;  // [max_iter]
-  const int32_t *done;
 };
 
-// Enqueue one iteration's move pass (async: hub flag snapshot, k_move, hub
-// merge; det: k_move).  Non-null events are recorded around k_move only.
-hipError_t launch_move(int k, bool async_mode, const MoveArgs &a, int grid,
-                       int merge_grid, hipStream_t s, hipEvent_t ev_beg,
-                       hipEvent_t ev_end);
+// Enqueue one iteration of every graph in the launch (async: hub flag
+// snapshot, k_move, hub merge; det: k_move; then the convergence test).
+// Non-null events are recorded around k_move only.
+hipError_t launch_iteration(int k, bool async_mode, const Launch &L, int grid, int merge_grid,
+                            hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
 int move_blocks_per_cu(int k, bool async_mode);
 
 }  // namespace lpa

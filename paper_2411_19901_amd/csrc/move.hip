@@ -355,33 +355,94 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st
   staged_mark<kStageT>(a, st, lane, beg, len, moved);
 }
 
-template <int K, bool ASYNC>
-__global__ __launch_bounds__(kBlock) void k_move(MoveArgs a) {
-  __shared__ Stage<kStageT> stage[kBlock / kWave];
-  if (*a.done) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wib = threadIdx.x / kWave;
-  const int wave = blockIdx.x * (kBlock / kWave) + wib;
-  const int nwaves = gridDim.x * (kBlock / kWave);
-  unsigned long long scanned_lane = 0, changed_w = 0, scanned_w = 0;
-  const int hub_items = ASYNC ? 0 : a.n_hubs;
-  const int units = (ASYNC ? a.n_seg : 0) + a.n_lane;
-  const int items = hub_items + (units + kWave - 1) / kWave;
-  for (int item = wave; item < items; item += nwaves) {
-    if (item < hub_items) {
-      hub_vertex_det<K>(a, a.order[item], scanned_w, changed_w);
-    } else {
-      const int u = (item - hub_items) * kWave + lane;
-      lane_units<K, ASYNC>(a, stage[wib], u, scanned_lane, changed_w);
-    }
+// ---------------------------------------------------------------------------
+// Multi-graph launches.  Work items of all graphs of a launch are numbered
+// consecutively; prefix[g] is the first item of graph g.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_graph(const int32_t *prefix, int G, int item) {
+  int lo = 0, hi = G;  // prefix[lo] <= item < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
   }
+  return lo;
+}
+
+__device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
+  MoveArgs a;
+  a.n = d.n;
+  a.row_ptr = d.row_ptr;
+  a.col = d.col;
+  a.w = d.w;
+  a.C = d.C[iter & 1];
+  a.Cn = d.C[(iter + 1) & 1];
+  a.act_cur = d.act[iter & 1];
+  a.act_next = d.act[(iter + 1) & 1];
+  a.order = d.order;
+  a.n_hubs = d.n_hubs;
+  a.n_lane = d.n_lane;
+  a.seg_len = d.seg_len;
+  a.n_seg = d.n_seg;
+  a.seg_hub = d.seg_hub;
+  a.hub_pbase = d.hub_pbase;
+  a.hub_act = d.hub_act;
+  a.part_key = d.part_key;
+  a.part_val = d.part_val;
+  a.iter = iter;
+  a.pickless = (d.rho > 0 && iter % d.rho == 0) ? 1 : 0;
+  return a;
+}
+
+// Add a wavefront's per-graph totals to the graph's counters (all lanes
+// call it together).
+__device__ __forceinline__ void flush_counts(unsigned long long *dN, unsigned long long *sc,
+                                             unsigned long long &scanned_lane,
+                                             unsigned long long &scanned_w,
+                                             unsigned long long &changed_w) {
 #pragma unroll
   for (int off = kWave / 2; off >= 1; off >>= 1) scanned_lane += __shfl_xor(scanned_lane, off);
-  if (lane == 0) {
-    const unsigned long long sc = scanned_lane + scanned_w;
-    if (sc) atomicAdd(a.scanned + a.iter, sc);
-    if (changed_w) atomicAdd(a.dN + a.iter, changed_w);
+  if ((threadIdx.x & (kWave - 1)) == 0 && dN) {
+    const unsigned long long t = scanned_lane + scanned_w;
+    if (t) atomicAdd(sc, t);
+    if (changed_w) atomicAdd(dN, changed_w);
   }
+  scanned_lane = scanned_w = changed_w = 0;
+}
+
+template <int K, bool ASYNC>
+__global__ __launch_bounds__(kBlock) void k_move(Launch L) {
+  __shared__ Stage<kStageT> stage[kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = rfl(threadIdx.x / kWave);
+  const int wave = rfl(blockIdx.x * (kBlock / kWave) + wib);
+  const int nwaves = gridDim.x * (kBlock / kWave);
+  unsigned long long scanned_lane = 0, changed_w = 0, scanned_w = 0;
+  int cur = -1;
+  unsigned long long *cdN = nullptr, *csc = nullptr;
+  for (int item = wave; item < L.total_items; item += nwaves) {
+    const int g = rfl(find_graph(L.prefix_items, L.G, item));
+    const GraphDesc &d = L.d[g];
+    if (d.st->done) continue;
+    const int iter = d.st->iter;
+    if (g != cur) {
+      flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
+      cur = g;
+      cdN = d.dN + iter;
+      csc = d.scanned + iter;
+    }
+    const MoveArgs a = make_args(d, iter);
+    const int local = item - L.prefix_items[g];
+    const int hub_items = ASYNC ? 0 : a.n_hubs;
+    if (local < hub_items)
+      hub_vertex_det<K>(a, a.order[local], scanned_w, changed_w);
+    else
+      lane_units<K, ASYNC>(a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane,
+                           changed_w);
+  }
+  flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,29 +451,44 @@ __global__ __launch_bounds__(kBlock) void k_move(MoveArgs a) {
 // Snapshot and clear the unprocessed flags of the hubs before the move
 // kernel, so that marks made while their segments are scanned are kept for
 // the next iteration.
-__global__ void k_hub_snapshot(MoveArgs a) {
-  if (*a.done) return;
-  for (int h = blockIdx.x * blockDim.x + threadIdx.x; h < a.n_hubs; h += gridDim.x * blockDim.x) {
-    const int v = a.order[h];
-    a.hub_act[h] = a.act_cur[v];
-    a.act_cur[v] = 0;
+__global__ void k_hub_snapshot(Launch L) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < L.total_hubs;
+       t += gridDim.x * blockDim.x) {
+    const int g = find_graph(L.prefix_hubs, L.G, t);
+    const GraphDesc &d = L.d[g];
+    if (d.st->done) continue;
+    const int h = t - L.prefix_hubs[g];
+    const int v = d.order[h];
+    d.hub_act[h] = d.act[0][v];
+    d.act[0][v] = 0;
   }
 }
 
 // Merge the partial sketches of every active hub (Section 4.3) and update
-// its label.  A wavefront takes 64 hubs: hubs with at most 64 partials are
-// merged by one lane each; larger ones by the whole wavefront (lane l merges
-// partials l, l + 64, ..., then a pairwise exchange across lanes).
+// its label.  A wavefront takes 64 hubs of one graph: hubs with at most 64
+// partials are merged by one lane each; larger ones by the whole wavefront
+// (lane l merges partials l, l + 64, ..., then a pairwise exchange across
+// lanes).
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_hub_merge(MoveArgs a) {
-  if (*a.done) return;
+__global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int wave = rfl((blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int nwaves = gridDim.x * (kBlock / kWave);
-  unsigned long long changed_w = 0;
-  const int items = (a.n_hubs + kWave - 1) / kWave;
-  for (int item = wave; item < items; item += nwaves) {
-    const int h = item * kWave + lane;
+  unsigned long long changed_w = 0, zero_lane = 0, zero_w = 0;
+  int cur = -1;
+  unsigned long long *cdN = nullptr;
+  for (int item = wave; item < L.total_merge; item += nwaves) {
+    const int g = rfl(find_graph(L.prefix_merge, L.G, item));
+    const GraphDesc &gd = L.d[g];
+    if (gd.st->done) continue;
+    const int iter = gd.st->iter;
+    if (g != cur) {
+      flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
+      cur = g;
+      cdN = gd.dN + iter;
+    }
+    const MoveArgs a = make_args(gd, iter);
+    const int h = (item - L.prefix_merge[g]) * kWave + lane;
     int v = -1, p0 = 0, np = 0, cv = 0;
     bool active = false;
     if (h < a.n_hubs) {
@@ -483,22 +559,48 @@ __global__ __launch_bounds__(kBlock) void k_hub_merge(MoveArgs a) {
       for (int e = rb + lane; e < re; e += kWave) mark(a, __builtin_nontemporal_load(a.col + e));
     }
   }
-  if (lane == 0 && changed_w) atomicAdd(a.dN + a.iter, changed_w);
+  flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
+}
+
+// Convergence test of Algorithm 1 for every graph of the launch: after
+// iteration l, stop when l is not a pick-less iteration and dN / N < tol,
+// or when max_iter iterations have run.
+__global__ void k_finish(Launch L) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < L.G; g += gridDim.x * blockDim.x) {
+    const GraphDesc &d = L.d[g];
+    GraphStatus *st = d.st;
+    if (!st->done) {
+      const int l = st->iter;
+      const bool pl = d.rho > 0 && l % d.rho == 0;
+      const double frac = (double)d.dN[l] / (double)d.n;
+      const bool stop = (!pl && frac < d.tol) || l + 1 >= d.max_iter;
+      st->iter = l + 1;
+      if (stop) {
+        st->done = 1;
+        atomicAdd(L.finished, 1);
+      }
+    }
+    L.status_out[2 * g] = st->iter;
+    L.status_out[2 * g + 1] = st->done;
+  }
 }
 
 // ---------------------------------------------------------------------------
 template <int K, bool ASYNC>
-static hipError_t launch_t(const MoveArgs &a, int grid, int merge_grid, hipStream_t s,
+static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_t s,
                            hipEvent_t ev_beg, hipEvent_t ev_end) {
   hipError_t e = hipSuccess;
-  if (ASYNC && a.n_hubs > 0)
-    hipLaunchKernelGGL(k_hub_snapshot, dim3((a.n_hubs + 255) / 256 < 1024 ? (a.n_hubs + 255) / 256 : 1024),
-                       dim3(256), 0, s, a);
+  if (ASYNC && L.total_hubs > 0) {
+    const int sg = (L.total_hubs + 255) / 256 < 1024 ? (L.total_hubs + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_hub_snapshot, dim3(sg), dim3(256), 0, s, L);
+  }
   if (ev_beg && (e = hipEventRecord(ev_beg, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, a);
+  if (L.total_items > 0) hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, L);
   if (ev_end && (e = hipEventRecord(ev_end, s)) != hipSuccess) return e;
-  if (ASYNC && a.n_hubs > 0)
-    hipLaunchKernelGGL((k_hub_merge<K>), dim3(merge_grid), dim3(kBlock), 0, s, a);
+  if (ASYNC && L.total_merge > 0)
+    hipLaunchKernelGGL((k_hub_merge<K>), dim3(merge_grid), dim3(kBlock), 0, s, L);
+  const int fg = (L.G + 255) / 256 < 64 ? (L.G + 255) / 256 : 64;
+  hipLaunchKernelGGL(k_finish, dim3(fg > 0 ? fg : 1), dim3(256), 0, s, L);
   return hipGetLastError();
 }
 
@@ -512,15 +614,15 @@ static int occ_t() {
 }
 
 template <bool ASYNC>
-static hipError_t launch_mode(int k, const MoveArgs &a, int grid, int merge_grid, hipStream_t s,
+static hipError_t launch_mode(int k, const Launch &L, int grid, int merge_grid, hipStream_t s,
                               hipEvent_t b, hipEvent_t e) {
   switch (k) {
-    case 1: return launch_t<1, ASYNC>(a, grid, merge_grid, s, b, e);
-    case 2: return launch_t<2, ASYNC>(a, grid, merge_grid, s, b, e);
-    case 4: return launch_t<4, ASYNC>(a, grid, merge_grid, s, b, e);
-    case 8: return launch_t<8, ASYNC>(a, grid, merge_grid, s, b, e);
-    case 16: return launch_t<16, ASYNC>(a, grid, merge_grid, s, b, e);
-    case 32: return launch_t<32, ASYNC>(a, grid, merge_grid, s, b, e);
+    case 1: return launch_t<1, ASYNC>(L, grid, merge_grid, s, b, e);
+    case 2: return launch_t<2, ASYNC>(L, grid, merge_grid, s, b, e);
+    case 4: return launch_t<4, ASYNC>(L, grid, merge_grid, s, b, e);
+    case 8: return launch_t<8, ASYNC>(L, grid, merge_grid, s, b, e);
+    case 16: return launch_t<16, ASYNC>(L, grid, merge_grid, s, b, e);
+    case 32: return launch_t<32, ASYNC>(L, grid, merge_grid, s, b, e);
     default: return hipErrorInvalidValue;
   }
 }
@@ -538,10 +640,10 @@ static int occ_mode(int k) {
   }
 }
 
-hipError_t launch_move(int k, bool async_mode, const MoveArgs &a, int grid, int merge_grid,
-                       hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
-  return async_mode ? launch_mode<true>(k, a, grid, merge_grid, s, ev_beg, ev_end)
-                    : launch_mode<false>(k, a, grid, merge_grid, s, ev_beg, ev_end);
+hipError_t launch_iteration(int k, bool async_mode, const Launch &L, int grid, int merge_grid,
+                            hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
+  return async_mode ? launch_mode<true>(k, L, grid, merge_grid, s, ev_beg, ev_end)
+                    : launch_mode<false>(k, L, grid, merge_grid, s, ev_beg, ev_end);
 }
 
 int move_blocks_per_cu(int k, bool async_mode) {

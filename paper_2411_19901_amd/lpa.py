@@ -44,7 +44,8 @@ class LpaGraph(ctypes.Structure):
 class LpaConfig(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("rho", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("lane_max_degree", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("check_every", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("reserved", ctypes.c_int32 * 4)]
 
 
 class LpaError(RuntimeError):
@@ -84,10 +85,19 @@ def load(path: str = LIB_PATH):
         "lpa_set_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                          ctypes.c_int]),
         "lpa_memory": (ctypes.c_int, [H, szp, szp]),
+        "lpa_progress": (ctypes.c_int, [H, ip, ip]),
         "lpa_profile": (ctypes.c_int, [H, ctypes.c_int]),
         "lpa_memory_floor": (ctypes.c_int, [H, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]),
         "lpa_get_profile": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_float), ctypes.c_int, ip]),
         "lpa_free": (ctypes.c_int, [H]),
+        "lpa_workspace_bytes": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int,
+                                               ctypes.c_int, ctypes.POINTER(LpaConfig), szp]),
+        "lpa_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(LpaConfig),
+                                            pH]),
+        "lpa_batch_step": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, i64p,
+                                          ip]),
+        "lpa_batch_run": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ip]),
+        "lpa_batch_free": (ctypes.c_int, [H]),
         "lpa_error_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lpa_last_error": (ctypes.c_char_p, [H]),
     }
@@ -189,6 +199,13 @@ def lpa_set_state(h, labels_ptr: int, flags_ptr: int, iteration: int, is_host: b
            "lpa_set_state", h)
 
 
+def lpa_progress(h) -> Tuple[int, bool]:
+    it = ctypes.c_int(0)
+    fin = ctypes.c_int(0)
+    _check(load().lpa_progress(h, ctypes.byref(it), ctypes.byref(fin)), "lpa_progress", h)
+    return int(it.value), bool(fin.value)
+
+
 def lpa_memory(h) -> Tuple[int, int]:
     core = ctypes.c_size_t(0)
     ev = ctypes.c_size_t(0)
@@ -219,6 +236,47 @@ def lpa_free(h) -> None:
         load().lpa_free(h)
 
 
+def lpa_workspace_bytes(n: int, nnz: int, k: int, max_iter: int, cfg: LpaConfig) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().lpa_workspace_bytes(n, nnz, k, max_iter, ctypes.byref(cfg), ctypes.byref(out)),
+           "lpa_workspace_bytes")
+    return int(out.value)
+
+
+def lpa_batch_create(capacity: int, k: int, cfg: LpaConfig):
+    b = ctypes.c_void_p()
+    _check(load().lpa_batch_create(capacity, k, ctypes.byref(cfg), ctypes.byref(b)),
+           "lpa_batch_create")
+    return b
+
+
+def _handle_array(handles):
+    arr = (ctypes.c_void_p * max(1, len(handles)))()
+    for i, h in enumerate(handles):
+        arr[i] = h.value if isinstance(h, ctypes.c_void_p) else h
+    return arr
+
+
+def lpa_batch_step(b, handles) -> Tuple[int, bool]:
+    ch = ctypes.c_int64(0)
+    dn = ctypes.c_int(0)
+    _check(load().lpa_batch_step(b, _handle_array(handles), len(handles), ctypes.byref(ch),
+                                 ctypes.byref(dn)), "lpa_batch_step")
+    return int(ch.value), bool(dn.value)
+
+
+def lpa_batch_run(b, handles) -> int:
+    it = ctypes.c_int(0)
+    _check(load().lpa_batch_run(b, _handle_array(handles), len(handles), ctypes.byref(it)),
+           "lpa_batch_run")
+    return int(it.value)
+
+
+def lpa_batch_free(b) -> None:
+    if b:
+        load().lpa_batch_free(b)
+
+
 # ----------------------------------------------------------------- wrapper
 class LPA:
     """One label-propagation problem on device-resident torch tensors.
@@ -230,7 +288,7 @@ class LPA:
     def __init__(self, row_ptr, col, weights=None, k: int = 8, tol: float = 0.05,
                  max_iter: int = 20, seed: int = 0, mode: str = "det", rho: int = 8,
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
-                 stream=None):
+                 stream=None, workspace=None):
         import torch
         for t, dt in ((row_ptr, torch.int32), (col, torch.int32)):
             if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
@@ -252,6 +310,12 @@ class LPA:
         cfg.stream = stream.cuda_stream
         cfg.lane_max_degree = lane_max_degree
         cfg.check_every = check_every
+        if workspace is not None:  # a uint8 CUDA tensor kept alive by this object
+            cfg.workspace = workspace.data_ptr()
+            cfg.workspace_bytes = workspace.numel()
+            self._keep = self._keep + (workspace,)
+        self.k = k
+        self.mode = mode
         with torch.cuda.device(self.device):
             self.h = lpa_init(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr() if self.nnz else 0,
                               weights.data_ptr() if weights is not None else None, k, tol,
@@ -293,6 +357,12 @@ class LPA:
         flags = np.ascontiguousarray(flags, np.uint8)
         lpa_set_state(self.h, labels.ctypes.data, flags.ctypes.data, iteration, True)
 
+    def iterations(self) -> int:
+        return lpa_progress(self.h)[0]
+
+    def finished(self) -> bool:
+        return lpa_progress(self.h)[1]
+
     def profile(self, enable: bool = True) -> None:
         lpa_profile(self.h, enable)
 
@@ -309,6 +379,50 @@ class LPA:
         if getattr(self, "h", None):
             lpa_free(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_bytes(n: int, nnz: int, k: int = 8, max_iter: int = 20, mode: str = "det",
+                    lane_max_degree: int = 0) -> int:
+    """Device bytes one handle needs (for LPA(..., workspace=...))."""
+    cfg = lpa_config_default()
+    cfg.flags = MODES[mode] | LPA_VALIDATE
+    cfg.lane_max_degree = lane_max_degree
+    return lpa_workspace_bytes(n, nnz, k, max_iter, cfg)
+
+
+class Batch:
+    """Runs iterations of many LPA handles with one set of launches per
+    iteration (see lpa_batch_create in include/lpa.h)."""
+
+    def __init__(self, capacity: int, k: int = 8, mode: str = "det", check_every: int = 0,
+                 stream=None, device=None):
+        import torch
+        cfg = lpa_config_default()
+        cfg.flags = MODES[mode]
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        cfg.stream = stream.cuda_stream
+        cfg.check_every = check_every
+        self.capacity = capacity
+        self.b = lpa_batch_create(capacity, k, cfg)
+
+    def step(self, solvers) -> Tuple[int, bool]:
+        return lpa_batch_step(self.b, [s.h for s in solvers])
+
+    def run(self, solvers) -> int:
+        return lpa_batch_run(self.b, [s.h for s in solvers])
+
+    def close(self) -> None:
+        if getattr(self, "b", None):
+            lpa_batch_free(self.b)
+            self.b = None
 
     def __del__(self):
         try:

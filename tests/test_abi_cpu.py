@@ -28,7 +28,8 @@ def test_config_default():
     cfg = lpa.lpa_config_default()
     assert cfg.flags == lpa.LPA_MODE_DET | lpa.LPA_VALIDATE
     assert cfg.rho == 8 and not cfg.stream and cfg.lane_max_degree == 0
-    assert cfg.check_every == 0 and list(cfg.reserved) == [0] * 6
+    assert cfg.check_every == 0 and not cfg.workspace and cfg.workspace_bytes == 0
+    assert list(cfg.reserved) == [0] * 4
 
 
 def _init(**kw):
@@ -70,3 +71,24 @@ def test_null_handle_calls():
     assert L.lpa_step(None, None, None) == lpa.LPA_ERR_ARG
     assert L.lpa_run(None, None) == lpa.LPA_ERR_ARG
     assert L.lpa_last_error(None) == b""
+
+
+def test_workspace_bytes_host_only():
+    det = lpa.workspace_bytes(1000, 20000, k=8, mode="det")
+    asy = lpa.workspace_bytes(1000, 20000, k=8, mode="async")
+    assert det > 1000 * 14 and asy > 1000 * 9
+    assert lpa.workspace_bytes(0, 0) > 0
+    L = lpa.load()
+    out = ctypes.c_size_t(0)
+    assert L.lpa_workspace_bytes(10, 20, 3, 20, None, ctypes.byref(out)) == lpa.LPA_ERR_UNSUPPORTED
+    assert L.lpa_workspace_bytes(-1, 20, 8, 20, None, ctypes.byref(out)) == lpa.LPA_ERR_ARG
+
+
+def test_batch_arguments():
+    L = lpa.load()
+    b = ctypes.c_void_p(7)
+    assert L.lpa_batch_create(0, 8, None, ctypes.byref(b)) == lpa.LPA_ERR_ARG
+    assert not b.value
+    assert L.lpa_batch_create(4, 5, None, ctypes.byref(b)) == lpa.LPA_ERR_UNSUPPORTED
+    assert L.lpa_batch_free(None) == lpa.LPA_OK
+    assert L.lpa_batch_run(None, None, 0, None) == lpa.LPA_ERR_ARG
