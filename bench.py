@@ -22,6 +22,7 @@ at iteration 0.
 """
 import argparse
 import json
+import math
 import os
 import re
 import sys
@@ -122,6 +123,166 @@ def build_graph(args):
     return g, name
 
 
+def bench_batch(args):
+    """512 planted-partition graphs (sizes log-uniform 1e3..2e5) solved in det
+    mode: one batched launch sequence vs one lpa_run per graph, identical
+    labels required."""
+    import hashlib
+
+    import numpy as np
+    import torch
+    from paper_2411_19901_amd import inputs, lpa
+
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    specs = inputs.batch_specs(args.batch_graphs, 512)
+    gs = [inputs.batch_graph(sp, 512, i) for i, sp in enumerate(specs)]
+    gen_s = time.perf_counter() - t
+    nv, ne = sum(g.n for g in gs), sum(g.nnz for g in gs)
+    log(f"[bench] batch of {len(gs)} graphs: {nv} vertices, {ne} entries, generated in {gen_s:.1f}s")
+    stream = torch.cuda.current_stream(dev)
+    t = time.perf_counter()
+    solvers = [lpa.LPA(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), None,
+                       k=args.k, tol=args.tol, max_iter=args.max_iter, mode=args.mode,
+                       stream=stream) for g in gs]
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t
+    batch = lpa.Batch(len(solvers), k=args.k, mode=args.mode, stream=stream)
+
+    def digest():
+        h = hashlib.sha256()
+        for s in solvers:
+            h.update(s.labels(device=False).tobytes())
+        return h.hexdigest()[:16]
+
+    def solo():
+        for s in solvers:
+            s.reset()
+            s.run()
+
+    def batched():
+        for s in solvers:
+            s.reset()
+        batch.run(solvers)
+
+    timings = {}
+    for name, fn in (("solo", solo), ("batched", batched)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        timings[name] = (time.perf_counter() - t0) / args.steps
+        timings[name + "_digest"] = digest()
+        timings[name + "_iters"] = [s.iterations() for s in solvers]
+    same = (timings["solo_digest"] == timings["batched_digest"]
+            and timings["solo_iters"] == timings["batched_iters"])
+    scanned = sum(int(s.trace()[1].sum()) for s in solvers)
+    res = {
+        "metric": "batched graphs/s", "value": round(len(gs) / timings["batched"], 2),
+        "unit": "graphs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(timings["batched"] * 1e3, 3), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"sbm-batch{len(gs)}-{args.mode}-k{args.k}", "graphs": len(gs),
+                   "vertices": nv, "nnz": ne, "k": args.k, "mode": args.mode,
+                   "step": "reset every handle + lpa_batch_run over all of them"},
+        "solo_graphs_per_s": round(len(gs) / timings["solo"], 2),
+        "solo_ms_per_step": round(timings["solo"] * 1e3, 3),
+        "speedup_vs_solo": round(timings["solo"] / timings["batched"], 3),
+        "identical_labels_and_iterations": bool(same),
+        "GTEPS_batched": round(scanned / timings["batched"] / 1e9, 3),
+        "init_s": round(init_s, 2), "gen_s": round(gen_s, 1),
+        "max_iterations": max(timings["batched_iters"]),
+    }
+    batch.close()
+    for s in solvers:
+        s.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_serve(args):
+    """Poisson stream of mixed requests (70% planted-partition graphs of
+    1e3..1e5 vertices, 30% R-MAT scale 14..max, weights uniform (0, 1]) served
+    with continuous batching vs one request at a time in arrival order."""
+    import numpy as np
+    import torch
+    from paper_2411_19901_amd import inputs, lpa
+    from paper_2411_19901_amd.serve import Backend, Server, poisson_arrivals
+
+    dev = torch.device("cuda:0")
+    rng_u = lambda i, j: inputs.uniform(5, i, j)  # noqa: E731
+    t = time.perf_counter()
+    gs = []
+    for i in range(args.requests):
+        if rng_u(i, 0) < 0.7:
+            n = int(math.exp(math.log(1e3) + rng_u(i, 1) * (math.log(1e5) - math.log(1e3))))
+            b = max(1, min(int(math.exp(math.log(8) + rng_u(i, 2) * (math.log(200) - math.log(8)))),
+                           n // 16))
+            g = inputs.batch_graph(inputs.BatchSpec(n, b), 5, i)
+        else:
+            g = inputs.rmat(14 + int(rng_u(i, 3) * (args.serve_max_scale - 13)), 16, seed=1000 + i)
+        gs.append(inputs.with_uniform_weights(g, i))
+    gen_s = time.perf_counter() - t
+    log(f"[bench] {len(gs)} requests generated in {gen_s:.1f}s "
+        f"({sum(g.nnz for g in gs)} entries)")
+    be = Backend(k=args.k, mode=args.mode, tol=args.tol, max_iter=args.max_iter,
+                 capacity=args.serve_slots)
+    # sequential service: one request at a time, each solved alone
+    seq_labels, seq_ms = [], []
+    for _ in range(args.warmup):
+        s = be.admit(Server(be).submit(gs[0].row_ptr, gs[0].col, gs[0].w))
+        s.run()
+        s.close()
+    for g in gs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        srv1 = Server(be, max_resident=1, hbm_reserve=0)
+        srv1.submit(g.row_ptr, g.col, g.w, arrival=0.0)
+        srv1.run_until_idle()
+        seq_ms.append((time.perf_counter() - t0) * 1e3)
+        seq_labels.append(srv1.completed[0].labels)
+    mu_seq = 1e3 / np.mean(seq_ms)  # requests per second, sequential
+    rate = args.serve_load * mu_seq
+    # sequential latency under the same Poisson arrivals (FIFO queue)
+    arr = poisson_arrivals(len(gs), rate, seed=5)
+    fin, clock = [], 0.0
+    for a, ms in zip(arr, seq_ms):
+        clock = max(clock, a) + ms / 1e3
+        fin.append(clock)
+    seq_lat = np.array(fin) - arr
+    seq_span = fin[-1] - arr[0]
+    # continuous batching
+    srv = Server(be, max_resident=args.serve_slots, hbm_reserve=1 << 30)
+    t0 = srv.clock()
+    for g, a in zip(gs, arr):
+        srv.submit(g.row_ptr, g.col, g.w, arrival=t0 + float(a))
+    srv.run_until_idle()
+    span = max(r.finished for r in srv.completed) - (t0 + arr[0])
+    by_id = {r.rid: r for r in srv.completed}
+    same = all(np.array_equal(by_id[i].labels, seq_labels[i]) for i in range(len(gs)))
+    st = srv.latency_stats()
+    res = {
+        "metric": "served graphs/s (p50/p99 latency)", "value": round(len(gs) / span, 2),
+        "unit": "graphs/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+        "ms_per_step": round(span * 1e3, 3), "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serve-mix{len(gs)}-{args.mode}-k{args.k}", "requests": len(gs),
+                   "arrival_rate_per_s": round(rate, 2), "load_vs_sequential": args.serve_load,
+                   "slots": args.serve_slots, "rmat_max_scale": args.serve_max_scale},
+        "p50_ms": round(st["p50_s"] * 1e3, 3), "p99_ms": round(st["p99_s"] * 1e3, 3),
+        "sequential": {"graphs_per_s": round(len(gs) / seq_span, 2),
+                       "p50_ms": round(float(np.percentile(seq_lat, 50)) * 1e3, 3),
+                       "p99_ms": round(float(np.percentile(seq_lat, 99)) * 1e3, 3),
+                       "mean_service_ms": round(float(np.mean(seq_ms)), 3)},
+        "identical_to_alone": bool(same), "ticks": srv.ticks,
+        "memory_waits": srv.waits_for_memory, "gen_s": round(gen_s, 1),
+    }
+    be.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +298,15 @@ def main():
     ap.add_argument("--lane-max-degree", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="graph", choices=["graph", "batch", "serve"],
+                    help="graph: one large graph (default); batch: many graphs per launch; "
+                         "serve: Poisson request stream with continuous batching")
+    ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--serve-load", type=float, default=0.9,
+                    help="arrival rate as a multiple of the sequential service rate")
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-max-scale", type=int, default=18)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -166,6 +336,14 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     lpa.load()  # fail loudly if the HIP library is missing
+    if args.workload == "batch":
+        if args.mode == "async" and "--mode" not in sys.argv:
+            args.mode = "det"
+        return bench_batch(args)
+    if args.workload == "serve":
+        if "--mode" not in sys.argv:
+            args.mode = "det"
+        return bench_serve(args)
     dev = torch.device("cuda:0")
     g, gname = build_graph(args)
     workload = f"{gname}-{args.mode}-k{args.k}"

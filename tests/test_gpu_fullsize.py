@@ -1,0 +1,96 @@
+"""Parity at the benchmark sizes.
+
+* R-MAT scale 22 (128M CSR entries), det mode: every iteration is checked in
+  full against the oracle's one-iteration function from the same state —
+  labels, next flags and changed count, bit for bit.
+* R-MAT scale 24 (0.52B entries, weights uniform in (0, 1]), det mode: two
+  iterations, checked on 200,000 sampled vertices plus every vertex of
+  degree above 4096 (the oracle chooses their labels one by one).
+* Modularity of the asynchronous run on R-MAT scale 24 (the benchmark
+  configuration) against the oracle's fp64 modularity of the same labels.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2411_19901_amd import inputs, lpa  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+_graphs = {}
+
+
+def graph(scale, weighted):
+    key = (scale, weighted)
+    if key not in _graphs:
+        g = inputs.rmat(scale)
+        _graphs[key] = inputs.with_uniform_weights(g, scale) if weighted else g
+    return _graphs[key]
+
+
+def solver(g, **kw):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    return lpa.LPA(torch.from_numpy(g.row_ptr).to(d), torch.from_numpy(g.col).to(d),
+                   torch.from_numpy(g.w).to(d) if g.w is not None else None, **kw)
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_det_every_iteration_exact():
+    g = graph(22, False)
+    s = solver(g, k=8, mode="det")
+    deg = g.degrees()
+    for it in range(20):
+        C, act, l = s.get_state()
+        ch, done = s.step()
+        C2, act2, l2 = s.get_state()
+        pl = l % 8 == 0
+        Cr, actr, dnr, scr = oracle.lpa_move(g.row_ptr, g.col, None, 8, pl, C, act)
+        assert ch == dnr, (l, ch, dnr)
+        assert np.array_equal(C2, Cr), l
+        nz = deg > 0  # flags of isolated vertices are unspecified
+        assert np.array_equal(act2[nz] != 0, actr[nz] != 0), l
+        dn, sc = s.trace()
+        assert sc[l] == scr
+        if done:
+            break
+    q = s.modularity()
+    assert abs(q - oracle.modularity(g.row_ptr, g.col, None, s.labels(device=False))) <= 1e-9
+    s.close()
+
+
+@pytest.mark.timeout(600)
+def test_rmat24_det_sampled():
+    g = graph(24, True)
+    s = solver(g, k=8, mode="det")
+    deg = g.degrees()
+    rng = np.random.default_rng(24)
+    nz = np.nonzero(deg > 0)[0]
+    sample = np.unique(np.concatenate([rng.choice(nz, 200_000, replace=False),
+                                       np.nonzero(deg > 4096)[0]])).astype(np.int32)
+    for _ in range(2):
+        C, act, l = s.get_state()
+        s.step()
+        C2, _, _ = s.get_state()
+        pl = l % 8 == 0
+        chosen = oracle.lpa_choose(g.row_ptr, g.col, g.w, 8, pl, C, sample)
+        expect = np.where(act[sample] != 0, chosen, C[sample])
+        bad = np.nonzero(C2[sample] != expect)[0]
+        assert bad.size == 0, (l, sample[bad[:5]], C2[sample[bad[:5]]], expect[bad[:5]])
+    s.close()
+
+
+@pytest.mark.timeout(600)
+def test_rmat24_async_modularity_parity():
+    g = graph(24, True)
+    s = solver(g, k=8, mode="async")
+    it = s.run()
+    assert 1 <= it <= 20
+    lab = s.labels(device=False)
+    assert lab.min() >= 0 and lab.max() < g.n
+    q = s.modularity()
+    assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, lab)) <= 1e-9
+    s.close()
