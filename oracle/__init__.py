@@ -92,6 +92,24 @@ def sketch_feed(k: int, labels, weights=None):
     return key, val
 
 
+#: value of ``k`` that selects the one-candidate vote of Algorithm 3
+BM_PAPER = -1
+
+
+def bm_paper_feed(labels, weights=None, init: int = -1):
+    """Feed a stream into the vote of Algorithm 3 starting at (init, 0);
+    returns (candidate, weight)."""
+    L = lib()
+    f = L.orc_bm_paper_feed
+    f.argtypes = [ctypes.c_int64, _i32p, _f32p, ctypes.c_int32, _f32p]
+    f.restype = ctypes.c_int32
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    weights = None if weights is None else np.ascontiguousarray(weights, dtype=np.float32)
+    wt = np.zeros(1, np.float32)
+    c = f(len(labels), _p(labels, _i32p), _p(weights, _f32p), init, _p(wt, _f32p))
+    return int(c), float(wt[0])
+
+
 def sketch_max_key(keys, vals, keep: int) -> int:
     keys = np.ascontiguousarray(keys, dtype=np.int32)
     vals = np.ascontiguousarray(vals, dtype=np.float32)
@@ -100,7 +118,8 @@ def sketch_max_key(keys, vals, keep: int) -> int:
 
 def lpa_run(row_ptr, col, w=None, k: int = 8, tol: float = 0.05, max_iter: int = 20,
             rho: int = 8, nthreads: int = 0):
-    """Algorithm 1 in Jacobi form; k=0 selects the exact argmax of Eq. 3.
+    """Algorithm 1 in Jacobi form; k=0 selects the exact argmax of Eq. 3,
+    k=BM_PAPER the vote of Algorithm 3.
 
     Returns (labels, iterations, dN_trace, scanned_trace)."""
     row_ptr, col, w = _csr(row_ptr, col, w)

@@ -30,6 +30,8 @@
  *      by pick-less is still processed.
  *   R5 N in dN/N is |V| (isolated vertices included); the comparison is
  *      strict and evaluated in double.
+ *   The paper's own Boyer-Moore rule (Algorithm 3) is available as a second
+ *   per-vertex rule (k == ORC_BM_PAPER), run by the same Jacobi driver.
  * fp32 arithmetic is plain IEEE single precision in program order (build
  * with -ffp-contract=off and without -ffast-math).  Modularity is fp64.
  */
@@ -113,6 +115,31 @@ void orc_sketch_feed(int k, int64_t len, const int32_t *labels, const float *w,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Weighted Boyer-Moore vote of Algorithm 3 (scan loop of its lpaMove).    */
+/* ---------------------------------------------------------------------- */
+
+static void bm_paper_step(int32_t *cand, float *wc, int32_t c, float w) {
+  if (c == *cand) {
+    *wc = *wc + w;
+  } else if (*wc > w) {
+    *wc = *wc - w;
+  } else {
+    *cand = c;
+    *wc = w;
+  }
+}
+
+int32_t orc_bm_paper_feed(int64_t len, const int32_t *labels, const float *w,
+                          int32_t init, float *weight) {
+  int32_t cand = init;
+  float wc = 0.0f;
+  for (int64_t t = 0; t < len; ++t)
+    bm_paper_step(&cand, &wc, labels[t], w ? w[t] : 1.0f);
+  if (weight) *weight = wc;
+  return cand;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Per-vertex choice: the label c@ a vertex would adopt.                    */
 /* ---------------------------------------------------------------------- */
 
@@ -128,6 +155,22 @@ static int32_t choose_sketch(int32_t i, const int32_t *row_ptr,
     orc_sketch_accumulate(k, key, val, C[j], w ? w[e] : 1.0f);
   }
   return orc_sketch_max_key(k, key, val, C[i]);
+}
+
+/* Algorithm 3 path: the candidate starts as the vertex's own label with
+ * weight 0 and sees the neighbours in CSR order, the vertex itself skipped;
+ * the final candidate is the choice. */
+static int32_t choose_bm_paper(int32_t i, const int32_t *row_ptr,
+                               const int32_t *col, const float *w,
+                               const int32_t *C) {
+  int32_t cand = C[i];
+  float wc = 0.0f;
+  for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    int32_t j = col[e];
+    if (j == i) continue;
+    bm_paper_step(&cand, &wc, C[j], w ? w[e] : 1.0f);
+  }
+  return cand;
 }
 
 /* Exact path (Eq. 3): K_{i->c} for every neighbouring label c, summed in
@@ -197,9 +240,9 @@ int64_t orc_lpa_move(int32_t n, const int32_t *row_ptr, const int32_t *col,
     for (int32_t i = 0; i < n; ++i) {
       if (!act[i]) continue; /* only unprocessed vertices */
       sc += row_ptr[i + 1] - row_ptr[i];
-      int32_t c = (k == 0)
-                      ? choose_exact(i, row_ptr, col, w, C, acc, touched)
-                      : choose_sketch(i, row_ptr, col, w, k, C, key, val);
+      int32_t c = (k == 0)   ? choose_exact(i, row_ptr, col, w, C, acc, touched)
+                  : (k < 0) ? choose_bm_paper(i, row_ptr, col, w, C)
+                            : choose_sketch(i, row_ptr, col, w, k, C, key, val);
       if (c != C[i] && (!pickless || c < C[i])) {
         C_next[i] = c;
         dN += 1;
@@ -224,7 +267,8 @@ int orc_lpa_run(int32_t n, const int32_t *row_ptr, const int32_t *col,
                 const float *w, int k, double tol, int max_iter, int rho,
                 int nthreads, int32_t *labels, int64_t *dN_trace,
                 int64_t *scanned_trace) {
-  if (n < 0 || k < 0 || k > 64 || max_iter < 0 || rho < 0) return -1;
+  if (n < 0 || (k < 0 && k != ORC_BM_PAPER) || k > 64 || max_iter < 0 || rho < 0)
+    return -1;
   for (int32_t i = 0; i < n; ++i) labels[i] = i; /* unique initial labels */
   if (dN_trace)
     for (int l = 0; l < max_iter; ++l) dN_trace[l] = 0;
@@ -278,9 +322,9 @@ void orc_lpa_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
 #pragma omp for schedule(dynamic, 64)
     for (int64_t q = 0; q < nv; ++q) {
       int32_t i = verts[q];
-      int32_t c = (k == 0)
-                      ? choose_exact(i, row_ptr, col, w, C, acc, touched)
-                      : choose_sketch(i, row_ptr, col, w, k, C, key, val);
+      int32_t c = (k == 0)   ? choose_exact(i, row_ptr, col, w, C, acc, touched)
+                  : (k < 0) ? choose_bm_paper(i, row_ptr, col, w, C)
+                            : choose_sketch(i, row_ptr, col, w, k, C, key, val);
       out[q] = (c != C[i] && (!pickless || c < C[i])) ? c : C[i];
     }
     free(acc);

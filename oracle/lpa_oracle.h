@@ -32,8 +32,21 @@ int32_t orc_sketch_max_key(int k, const int32_t *key, const float *val,
 void orc_sketch_feed(int k, int64_t len, const int32_t *labels, const float *w,
                      int32_t *key, float *val);
 
+/* The weighted Boyer-Moore vote exactly as Algorithm 3 (lpaMove scan loop)
+ * states it: the candidate starts as (init, 0); a pair (c, w) adds w when c
+ * is the candidate, else subtracts w when the candidate's weight exceeds w,
+ * else replaces the candidate by (c, w).  Returns the final candidate and
+ * stores its weight in *weight. */
+int32_t orc_bm_paper_feed(int64_t len, const int32_t *labels, const float *w,
+                          int32_t init, float *weight);
+
+/* Value of k that selects the rule of Algorithm 3 (one candidate) in the
+ * functions below. */
+#define ORC_BM_PAPER (-1)
+
 /* One synchronous (Jacobi) iteration of Algorithm 1's lpaMove.
- * k >= 1: k-slot sketch; k == 0: exact argmax of Eq. 3 (dense accumulator).
+ * k >= 1: k-slot sketch; k == 0: exact argmax of Eq. 3 (dense accumulator);
+ * k == ORC_BM_PAPER: the vote of Algorithm 3.
  * Reads C and act, writes C_next and act_next (act_next must be zeroed by
  * the caller).  Returns the number of changed vertices; *scanned receives
  * the number of CSR entries read by the neighbourhood scans. */
