@@ -75,6 +75,17 @@ typedef enum lpa_status {
  * invalid graph is undefined behaviour (out-of-range reads).  Symmetry is
  * expected but never checked. */
 #define LPA_VALIDATE 0x100u
+/* Replace the sketch by the paper's one-candidate weighted Boyer-Moore vote
+ * (Section 4.7, Algorithm 3, nu-BM-LPA): the candidate starts as the
+ * vertex's own label with weight 0; a neighbour pair (c, w) adds w when c is
+ * the candidate, subtracts w when the candidate's weight is larger than w,
+ * and otherwise becomes the candidate with weight w.  The final candidate is
+ * the choice (pick-less and pruning as for the sketch).  Requires k == 1
+ * (LPA_ERR_ARG otherwise).  LPA_MODE_DET feeds every vertex in CSR order
+ * (bit-identical to the CPU definition); LPA_MODE_ASYNC splits high-degree
+ * vertices into segments whose candidates are combined by the largest
+ * weight, ties to the lowest label (the paper's pair-max reduction). */
+#define LPA_RULE_BM_PAPER 0x200u
 
 /* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji). */
 typedef struct lpa_graph {
@@ -85,7 +96,8 @@ typedef struct lpa_graph {
 } lpa_graph;
 
 typedef struct lpa_config {
-  uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC, | LPA_VALIDATE */
+  uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC,
+                              | LPA_VALIDATE, | LPA_RULE_BM_PAPER */
   int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per

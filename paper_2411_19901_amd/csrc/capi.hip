@@ -196,69 +196,7 @@ __device__ __forceinline__ double wave_sum_d(double x) {
   return x;
 }
 
-// acc[0] += K_i (sum = 2m), acc[1] += intra-community weight, tot[C_i] += K_i
-__global__ void k_mod_lane(const int32_t *order, int first, int count, const int32_t *rp,
-                           const int32_t *col, const float *w, const int32_t *lab, int n,
-                           double *tot, double *acc, int *bad) {
-  double k_sum = 0.0, in_sum = 0.0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-    const int i = order[first + t];
-    const int ci = lab[i];
-    if (ci < 0 || ci >= n) {
-      atomicOr(bad, 8);
-      continue;
-    }
-    double ki = 0.0, in = 0.0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) {
-      const double x = w ? (double)w[e] : 1.0;
-      ki += x;
-      if (lab[col[e]] == ci) in += x;
-    }
-    atomicAdd(&tot[ci], ki);
-    k_sum += ki;
-    in_sum += in;
-  }
-  k_sum = wave_sum_d(k_sum);
-  in_sum = wave_sum_d(in_sum);
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&acc[0], k_sum);
-    atomicAdd(&acc[1], in_sum);
-  }
-}
-
-__global__ void k_mod_hub(const int32_t *order, int count, const int32_t *rp, const int32_t *col,
-                          const float *w, const int32_t *lab, int n, double *tot, double *acc,
-                          int *bad) {
-  const int lane = threadIdx.x & 63;
-  const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nw = (gridDim.x * blockDim.x) >> 6;
-  double k_sum = 0.0, in_sum = 0.0;  // lane partial sums over this wave's hubs
-  for (int t = wid; t < count; t += nw) {
-    const int i = order[t];
-    const int ci = lab[i];
-    if (ci < 0 || ci >= n) {
-      if (lane == 0) atomicOr(bad, 8);
-      continue;
-    }
-    double ki = 0.0;
-    for (int e = rp[i] + lane; e < rp[i + 1]; e += 64) {
-      const double x = w ? (double)w[e] : 1.0;
-      ki += x;
-      if (lab[col[e]] == ci) in_sum += x;
-    }
-    k_sum += ki;
-    ki = wave_sum_d(ki);
-    if (lane == 0) atomicAdd(&tot[ci], ki);
-  }
-  k_sum = wave_sum_d(k_sum);
-  in_sum = wave_sum_d(in_sum);
-  if (lane == 0) {
-    atomicAdd(&acc[0], k_sum);
-    atomicAdd(&acc[1], in_sum);
-  }
-}
-
-// acc[2] += sum_c tot[c]^2; clears tot for the next call
+// Sum of squares of the community totals (then cleared for the next call).
 __global__ void k_mod_sq(double *tot, int n, double *acc) {
   double s = 0.0;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
@@ -303,7 +241,7 @@ int grid_for(size_t count, int block = kAuxBlock, int cap = 4096) {
 // ===========================================================================
 struct lpa_batch {
   int capacity = 0;
-  int k = 8;
+  int k = 8;  // kernel selector: sketch slots, 0 = the vote of Algorithm 3
   bool async_mode = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -353,6 +291,7 @@ struct lpa_handle {
   uint32_t *hist = nullptr;  // binning scratch
   int32_t seg_cap = 0, hub_cap = 0;
   double *mod_tot = nullptr;
+  int mod_grid = 0;  // k_modularity workgroups (resident on every CU)
   double *mod_acc = nullptr;
   std::vector<void *> eval_allocs;
 
@@ -407,6 +346,17 @@ int fail_hip_b(lpa_batch *b, hipError_t e, const char *what) {
   } while (0)
 
 bool k_supported(int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32; }
+
+// Check k against the rule flags: LPA_ERR_UNSUPPORTED for a k without
+// kernels, LPA_ERR_ARG for the one-candidate vote with k != 1.
+int check_k(int k, uint32_t flags) {
+  if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
+  if ((flags & LPA_RULE_BM_PAPER) && k != 1) return LPA_ERR_ARG;
+  return LPA_OK;
+}
+
+// Kernel selector: k slots, or 0 for the vote of Algorithm 3.
+int kernel_k(int k, uint32_t flags) { return (flags & LPA_RULE_BM_PAPER) ? 0 : k; }
 
 int check_ready(lpa_handle *h) {
   if (!h) return LPA_ERR_ARG;
@@ -551,7 +501,7 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
     lpa_handle *h = hs[g];
     if (!h) return LPA_ERR_ARG;
     if (h->poisoned) return LPA_ERR_HIP;
-    if (h->k != b->k || h->async_mode != b->async_mode || h->device != b->device ||
+    if (kernel_k(h->k, h->flags) != b->k || h->async_mode != b->async_mode || h->device != b->device ||
         h->stream != b->stream)
       return LPA_ERR_ARG;
     for (int q = 0; q < g; ++q)
@@ -696,7 +646,8 @@ static int check_config(const lpa_config &cfg) {
     return LPA_ERR_ARG;
   const uint32_t mode = cfg.flags & LPA_MODE_MASK;
   if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
-  if ((cfg.flags & ~(LPA_MODE_MASK | LPA_VALIDATE)) != 0) return LPA_ERR_UNSUPPORTED;
+  if ((cfg.flags & ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER)) != 0)
+    return LPA_ERR_UNSUPPORTED;
   if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
   return LPA_OK;
 }
@@ -712,7 +663,7 @@ int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter, const lpa_c
   if (n < 0 || nnz < 0 || nnz >= (int64_t)INT32_MAX || max_iter < 0) return LPA_ERR_ARG;
   int rc = check_config(cfg);
   if (rc) return rc;
-  if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
+  if ((rc = check_k(k, cfg.flags)) != LPA_OK) return rc;
   const bool async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   const int lane_max = cfg.lane_max_degree > 0 ? cfg.lane_max_degree : default_lane_max(async_mode);
   *bytes = plan_layout(n, nnz, k, max_iter, async_mode, lane_max).total;
@@ -748,7 +699,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   if (g->nnz > 0 && !g->col_idx) return LPA_ERR_ARG;
   if (g->n == 0 && g->nnz != 0) return LPA_ERR_ARG;
   if (!(tol >= 0.0 && tol <= 1.0) || max_iter < 0) return LPA_ERR_ARG;
-  if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
+  if ((rc = check_k(k, cfg.flags)) != LPA_OK) return rc;
 
   lpa_handle *h = new (std::nothrow) lpa_handle();
   if (!h) return LPA_ERR_NOMEM;
@@ -880,7 +831,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   h->self = new (std::nothrow) lpa_batch();
   if (!h->self) return bail(LPA_ERR_NOMEM);
   h->self->capacity = 1;
-  h->self->k = k;
+  h->self->k = kernel_k(k, cfg.flags);
   h->self->async_mode = h->async_mode;
   h->self->stream = h->stream;
   h->self->check_every = h->check_every;
@@ -944,11 +895,11 @@ int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **
     lpa_config_default(&cfg);
   int rc = check_config(cfg);
   if (rc) return rc;
-  if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
+  if ((rc = check_k(k, cfg.flags)) != LPA_OK) return rc;
   lpa_batch *b = new (std::nothrow) lpa_batch();
   if (!b) return LPA_ERR_NOMEM;
   b->capacity = capacity;
-  b->k = k;
+  b->k = kernel_k(k, cfg.flags);
   b->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   b->stream = (hipStream_t)cfg.stream;
   b->check_every = cfg.check_every;
@@ -1063,32 +1014,39 @@ int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q) {
   }
   const int32_t *lab = labels ? labels : cur_labels(h);
   const GraphDesc &d = h->desc;
-  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, h->stream, h->mod_acc, 4);
   hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
-  if (d.n_hubs > 0)
-    hipLaunchKernelGGL(k_mod_hub, dim3(grid_for((size_t)d.n_hubs * 64, kAuxBlock, 2048)),
-                       dim3(kAuxBlock), 0, h->stream, d.order, d.n_hubs, h->row_ptr, h->col, h->w,
-                       lab, n, h->mod_tot, h->mod_acc, &h->st->err);
-  if (d.n_lane > 0)
-    hipLaunchKernelGGL(k_mod_lane, dim3(grid_for(d.n_lane, kAuxBlock, 4096)), dim3(kAuxBlock), 0,
-                       h->stream, d.order, d.n_hubs, d.n_lane, h->row_ptr, h->col, h->w, lab, n,
-                       h->mod_tot, h->mod_acc, &h->st->err);
+  if (labels) {  // the library's own labels are in range by construction
+    hipLaunchKernelGGL(k_check_labels, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, labels, n,
+                       &h->st->err);
+    LAUNCH_TRY(h, "label check");
+    int bad = 0;
+    HIP_TRY(h, hipMemcpyAsync(&bad, &h->st->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (bad) {
+      hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
+      LAUNCH_TRY(h, "label check reset");
+      return set_err(h, LPA_ERR_GRAPH, "label out of range [0, n)");
+    }
+  }
+  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, h->stream, h->mod_acc, 4);
+  ModArgs m;
+  m.order = d.order;
+  m.n_hubs = d.n_hubs;
+  m.n_lane = d.n_lane;
+  m.row_ptr = h->row_ptr;
+  m.col = h->col;
+  m.w = h->w;
+  m.lab = lab;
+  m.tot = h->mod_tot;
+  m.acc = h->mod_acc;
+  if (h->mod_grid == 0) h->mod_grid = h->self->cus * modularity_blocks_per_cu();
+  HIP_TRY(h, launch_modularity(m, h->mod_grid, h->stream));
   hipLaunchKernelGGL(k_mod_sq, dim3(grid_for(n, kAuxBlock, 4096)), dim3(kAuxBlock), 0, h->stream,
                      h->mod_tot, n, h->mod_acc);
   LAUNCH_TRY(h, "modularity kernels");
   double acc[4] = {0, 0, 0, 0};
-  int bad = 0;
   HIP_TRY(h, hipMemcpyAsync(acc, h->mod_acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(&bad, &h->st->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  if (bad) {
-    // out-of-range labels were skipped, so the per-community totals may be
-    // partial: clear them for the next call
-    hipLaunchKernelGGL(k_zero_d, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->mod_tot, n);
-    hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
-    LAUNCH_TRY(h, "modularity reset");
-    return set_err(h, LPA_ERR_GRAPH, "label out of range [0, n)");
-  }
   const double two_m = acc[0];
   *q = two_m > 0.0 ? acc[1] / two_m - acc[2] / (two_m * two_m) : 0.0;
   return LPA_OK;

@@ -102,11 +102,31 @@ struct MoveArgs {
   int32_t pickless;
 };
 
+// Kernel selector: k slots of the weighted Misra-Gries sketch, or 0 for the
+// one-candidate vote of Algorithm 3 (LPA_RULE_BM_PAPER).
 // Enqueue one iteration of every graph in the launch (async: hub flag
 // snapshot, k_move, hub merge; det: k_move; then the convergence test).
 // Non-null events are recorded around k_move only.
 hipError_t launch_iteration(int k, bool async_mode, const Launch &L, int grid, int merge_grid,
                             hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
 int move_blocks_per_cu(int k, bool async_mode);
+
+// Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read
+// by one wavefront each, order[n_hubs, n_hubs + n_lane) one lane each.
+// Labels must lie in [0, n).  acc[0] += 2m, acc[1] += sigma,
+// tot[c] += K_i for every vertex i labelled c.
+struct ModArgs {
+  const int32_t *order;
+  int32_t n_hubs;
+  int32_t n_lane;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const float *w;
+  const int32_t *lab;
+  double *tot;
+  double *acc;
+};
+hipError_t launch_modularity(const ModArgs &m, int grid, hipStream_t s);
+int modularity_blocks_per_cu();
 
 }  // namespace lpa

@@ -33,22 +33,13 @@
 // written when c is in no slot.  A weight of 0 leaves the sketch unchanged,
 // which is how self-loops and padding are skipped without a branch.
 #include "lpa_internal.h"
+#include "wave.h"
 
 #include <limits.h>
 #include <math.h>
 
 namespace lpa {
 
-__device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ float rfl_f(float x) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
-}
-// Order LDS accesses of this wavefront: the wavefront executes its LDS
-// instructions in order, this only keeps the compiler from moving them.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // ---------------------------------------------------------------------------
 // Register sketch: one lane owns all K slots.
@@ -115,76 +106,59 @@ struct LaneSketch {
 };
 
 // ---------------------------------------------------------------------------
-// Wave sketch: lane s < K owns slot s; every lane sees the same (c, w).
+// The weighted Boyer-Moore vote of Algorithm 3 (nu-BM-LPA): one candidate
+// (key, val).  A pair (c, w) adds w when c is the candidate, subtracts w when
+// the candidate's weight is larger, and otherwise becomes the candidate.
+// The paper starts the candidate at (C[i], 0); starting at (-1, 0) gives the
+// same result: from weight 0 the first positive pair becomes (c, w) either
+// way, a zero-weight pair leaves a weight-0 candidate empty in effect, and
+// a positive weight never returns to 0 (val > w implies val - w > 0 with
+// denormals kept).  So an empty vote keeps the current label.
+// Selected by K = 0 in the kernels below.
 // ---------------------------------------------------------------------------
-template <int K>
-__device__ __forceinline__ void wave_sketch_add(int &key, float &val, int c, float w, int lane) {
-  const bool mine = lane < K;
-  const bool eq = mine && key == c;
-  if (__ballot(eq)) {
-    if (eq) val = val + w;
-    return;
-  }
-  unsigned long long z = __ballot(mine && val == 0.0f);
-  float r = w;
-  if (z == 0ull) {
-    float m = mine ? val : INFINITY;
-#pragma unroll
-    for (int off = K / 2; off >= 1; off >>= 1) m = fminf(m, __shfl_xor(m, off));
-    const float d = fminf(w, rfl_f(m));
-    if (mine) val = val - d;
-    r = w - d;
-    if (!(r > 0.0f)) return;
-    z = __ballot(mine && val == 0.0f);
-  }
-  const int s = __ffsll((long long)z) - 1;
-  if (lane == s) {
-    key = c;
-    val = r;
-  }
-}
+struct BmSketch {
+  int key[1];
+  float val[1];
 
-template <int K>
-__device__ __forceinline__ int wave_max_key(int key, float val, int lane, int keep) {
-  const bool live = lane < K && val > 0.0f;
-  float bv = live ? val : 0.0f;
-  int bk = live ? key : INT_MAX;
-#pragma unroll
-  for (int off = K / 2; off >= 1; off >>= 1) {
-    const float ov = __shfl_xor(bv, off);
-    const int ok = __shfl_xor(bk, off);
-    const bool better = ov > bv || (ov == bv && ok < bk);
-    bv = better ? ov : bv;
-    bk = better ? ok : bk;
+  __device__ __forceinline__ void clear() {
+    key[0] = -1;
+    val[0] = 0.0f;
   }
-  bv = rfl_f(bv);
-  bk = rfl(bk);
-  return bv > 0.0f ? bk : keep;
-}
 
-// ---------------------------------------------------------------------------
-// LDS staging of 64 rows, T entries per row per step.
-// ---------------------------------------------------------------------------
-template <int T>
-struct Stage {
-  int beg[kWave];
-  int len[kWave];
-  int self[kWave];
-  int lab[kWave * (T + 1)];
-  float w[kWave * (T + 1)];
+  __device__ __forceinline__ void add(int c, float w) {
+    const bool same = key[0] == c;
+    const bool down = !same && val[0] > w;
+    val[0] = same ? val[0] + w : (down ? val[0] - w : w);
+    key[0] = (same || down) ? key[0] : c;
+  }
+
+  __device__ __forceinline__ int max_key(int keep) const { return val[0] > 0.0f ? key[0] : keep; }
+
+  // Partial votes of one hub combine by the largest weight (ties to the
+  // lowest label), as the paper's pair-max block reduction does.
+  __device__ __forceinline__ void merge_from(const int *pk, const float *pv) {
+    const bool better = pv[0] > val[0] || (pv[0] == val[0] && pv[0] > 0.0f && pk[0] < key[0]);
+    key[0] = better ? pk[0] : key[0];
+    val[0] = better ? pv[0] : val[0];
+  }
 };
 
-__device__ __forceinline__ int wave_max(int x) {
-#pragma unroll
-  for (int off = kWave / 2; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off));
-  return x;
-}
+template <int K>
+struct SketchOf {
+  using type = LaneSketch<K>;
+};
+template <>
+struct SketchOf<0> {
+  using type = BmSketch;
+};
+// Slots stored per partial sketch.
+constexpr int slots_of(int K) { return K == 0 ? 1 : K; }
 
 // Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
 // nothing).  All lanes of the wavefront must call it together.
-template <int K, int T>
+template <class SK, int T>
 __device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T> &st, int lane, int beg,
-                                            int len, int self, LaneSketch<K> &S) {
+                                            int len, int self, SK &S) {
   st.beg[lane] = beg;
   st.len[lane] = len;
   st.self[lane] = self;
@@ -209,8 +183,12 @@ __device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T> &st, int
       st.w[r * (T + 1) + j] = x;
     }
     wave_lds_sync();
+    // columns past the longest row of the wavefront hold only padding
+    // (weight 0, a no-op), so the uniform bound tn skips them
+    const int tn = min(T, maxlen - t0);
 #pragma unroll
-    for (int j = 0; j < T; ++j) S.add(st.lab[lane * (T + 1) + j], st.w[lane * (T + 1) + j]);
+    for (int j = 0; j < T; ++j)
+      if (j < tn) S.add(st.lab[lane * (T + 1) + j], st.w[lane * (T + 1) + j]);
     wave_lds_sync();
   }
 }
@@ -241,11 +219,19 @@ __device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T> &st, int
   wave_lds_sync();
 }
 
-constexpr int kStageT = 16;
-
 // ---------------------------------------------------------------------------
 // LPA_MODE_DET hub path: one wavefront per vertex, CSR order.
+//
+// Lane s < K holds slot s.  The wavefront loads 64 consecutive entries
+// (lane t holds entry base + t), then every lane finds the slot whose key
+// equals its label (at most one: keys are unique).  Entries are consumed in
+// lane order: a run of entries whose label is already a key only adds
+// weights to those slots, so it is applied entry by entry with scalar lane
+// indices and no cross-lane votes; the first entry without a key takes the
+// full sketch step, after which only the lanes whose label was the replaced
+// key or is the new key change their slot.
 // ---------------------------------------------------------------------------
+
 template <int K>
 __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &scanned,
                                unsigned long long &changed) {
@@ -263,8 +249,8 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
   int nlab = 0;
   float nw = 0.0f;
   if (e < end) {
-    const int j = a.col[e];
-    nw = (j == v) ? 0.0f : (a.w ? a.w[e] : 1.0f);
+    const int j = __builtin_nontemporal_load(a.col + e);
+    nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
     nlab = a.C[j];
   }
   for (int base = beg; base < end; base += kWave) {
@@ -273,19 +259,112 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
     // prefetch the next 64 neighbours while this block is consumed
     e = base + kWave + lane;
     if (e < end) {
-      const int j = a.col[e];
-      nw = (j == v) ? 0.0f : (a.w ? a.w[e] : 1.0f);
+      const int j = __builtin_nontemporal_load(a.col + e);
+      nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
       nlab = a.C[j];
     }
     const int cnt = min(kWave, end - base);
-    for (int t = 0; t < cnt; ++t) {
-      const int c = __builtin_amdgcn_readlane(lab, t);
-      const float xw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), t));
-      if (xw == 0.0f) continue;
-      wave_sketch_add<K>(key, val, c, xw, lane);
+    int slot = -1;  // the slot holding this lane's label, if any
+#pragma unroll
+    for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
+    unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
+    while (pend) {
+      const unsigned long long missm = __ballot(slot < 0) & pend;
+      // entries before the first miss only add to existing slots
+      unsigned long long run = missm ? (pend & ((missm & (~missm + 1)) - 1)) : pend;
+      pend &= ~run;
+      while (run) {
+        const int h = __ffsll((long long)run) - 1;
+        run &= run - 1;
+        const int sh = rl(slot, h);
+        const float xh = rl_f(x, h);
+        if (lane == sh) val = val + xh;
+      }
+      if (!missm) break;
+      const int jm = __ffsll((long long)missm) - 1;
+      pend &= ~(1ull << jm);
+      const int c = rl(lab, jm);
+      const float xw = rl_f(x, jm);
+      unsigned long long z = __ballot(lane < K && val == 0.0f);
+      float r = xw;
+      if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
+        float m = xw;
+#pragma unroll
+        for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+        if (lane < K) val = val - m;
+        r = xw - m;
+        z = r > 0.0f ? __ballot(lane < K && val == 0.0f) : 0ull;
+      }
+      if (z) {  // the (residue of the) pair takes a free slot
+        const int s = __ffsll((long long)z) - 1;
+        const int old = rl(key, s);
+        if (lane == s) {
+          key = c;
+          val = r;
+        }
+        slot = (lab == old) ? -1 : slot;
+        slot = (lab == c) ? s : slot;
+      }
     }
   }
-  const int c = wave_max_key<K>(key, val, lane, cv);
+  // heaviest live slot, ties to the lowest label; keep when empty
+  int bk = cv;
+  float bv = 0.0f;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const float vs = rl_f(val, s);
+    const int ks = rl(key, s);
+    if (vs > bv || (vs == bv && vs > 0.0f && ks < bk)) {
+      bk = ks;
+      bv = vs;
+    }
+  }
+  const int c = bk;
+  const bool moved = c != cv && (!a.pickless || c < cv);
+  if (lane == 0) a.Cn[v] = moved ? c : cv;
+  if (moved) {
+    changed += 1;
+    for (int q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
+  }
+  scanned += (unsigned long long)(end - beg);
+}
+
+// LPA_MODE_DET hub path for the vote of Algorithm 3: the wavefront loads 64
+// consecutive entries at a time and the vote consumes them in CSR order
+// through lane reads (every lane holds the same candidate).
+__device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &scanned,
+                                  unsigned long long &changed) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int cv = a.C[v];
+  if (a.act_cur[v] == 0) {
+    if (lane == 0) a.Cn[v] = cv;
+    return;
+  }
+  if (lane == 0) a.act_cur[v] = 0;
+  const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+  BmSketch S;
+  S.clear();
+  int e = beg + lane;
+  int nlab = 0;
+  float nw = 0.0f;
+  if (e < end) {
+    const int j = __builtin_nontemporal_load(a.col + e);
+    nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
+    nlab = a.C[j];
+  }
+  for (int base = beg; base < end; base += kWave) {
+    const int lab = nlab;
+    const float x = nw;
+    e = base + kWave + lane;
+    if (e < end) {
+      const int j = __builtin_nontemporal_load(a.col + e);
+      nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
+      nlab = a.C[j];
+    }
+    const int cnt = min(kWave, end - base);
+    for (int t = 0; t < cnt; ++t) S.add(rl(lab, t), rl_f(x, t));
+  }
+  const int c = S.max_key(cv);
   const bool moved = c != cv && (!a.pickless || c < cv);
   if (lane == 0) a.Cn[v] = moved ? c : cv;
   if (moved) {
@@ -328,17 +407,18 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st
     }
   }
   if (!active) len = 0;
-  LaneSketch<K> S;
+  typename SketchOf<K>::type S;
   S.clear();
-  staged_scan<K, kStageT>(a, st, lane, beg, len, v, S);
+  staged_scan<typename SketchOf<K>::type, kStageT>(a, st, lane, beg, len, v, S);
   scanned += (unsigned long long)len;
   bool moved = false;
   if (pslot >= 0) {
     if (active) {  // partial sketch of one hub segment
+      constexpr int P = slots_of(K);
 #pragma unroll
-      for (int s = 0; s < K; ++s) {
-        a.part_key[(size_t)pslot * K + s] = S.key[s];
-        a.part_val[(size_t)pslot * K + s] = S.val[s];
+      for (int s = 0; s < P; ++s) {
+        a.part_key[(size_t)pslot * P + s] = S.key[s];
+        a.part_val[(size_t)pslot * P + s] = S.val[s];
       }
     }
   } else if (whole) {
@@ -436,9 +516,12 @@ __global__ __launch_bounds__(kBlock) void k_move(Launch L) {
     const MoveArgs a = make_args(d, iter);
     const int local = item - L.prefix_items[g];
     const int hub_items = ASYNC ? 0 : a.n_hubs;
-    if (local < hub_items)
-      hub_vertex_det<K>(a, a.order[local], scanned_w, changed_w);
-    else
+    if (local < hub_items) {
+      if constexpr (K == 0)
+        hub_vertex_det_bm(a, a.order[local], scanned_w, changed_w);
+      else
+        hub_vertex_det<K>(a, a.order[local], scanned_w, changed_w);
+    } else
       lane_units<K, ASYNC>(a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane,
                            changed_w);
   }
@@ -498,18 +581,20 @@ __global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
       np = a.hub_pbase[h + 1] - p0;
       cv = a.C[v];
     }
+    using SK = typename SketchOf<K>::type;
+    constexpr int P = slots_of(K);
     int c = cv;
     const bool small = active && np <= kWave;
-    LaneSketch<K> S;
+    SK S;
     S.clear();
     if (small) {
       for (int p = p0; p < p0 + np; ++p) {
-        int pk[K];
-        float pv[K];
+        int pk[P];
+        float pv[P];
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-          pk[s] = a.part_key[(size_t)p * K + s];
-          pv[s] = a.part_val[(size_t)p * K + s];
+        for (int s = 0; s < P; ++s) {
+          pk[s] = a.part_key[(size_t)p * P + s];
+          pv[s] = a.part_val[(size_t)p * P + s];
         }
         S.merge_from(pk, pv);
       }
@@ -520,24 +605,24 @@ __global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
       const int src = __ffsll((long long)big) - 1;
       big &= big - 1;
       const int bp0 = __shfl(p0, src), bnp = __shfl(np, src), bcv = __shfl(cv, src);
-      LaneSketch<K> B;
+      SK B;
       B.clear();
       for (int p = bp0 + lane; p < bp0 + bnp; p += kWave) {
-        int pk[K];
-        float pv[K];
+        int pk[P];
+        float pv[P];
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-          pk[s] = a.part_key[(size_t)p * K + s];
-          pv[s] = a.part_val[(size_t)p * K + s];
+        for (int s = 0; s < P; ++s) {
+          pk[s] = a.part_key[(size_t)p * P + s];
+          pv[s] = a.part_val[(size_t)p * P + s];
         }
         B.merge_from(pk, pv);
       }
 #pragma unroll 1
       for (int off = kWave / 2; off >= 1; off >>= 1) {
-        int pk[K];
-        float pv[K];
+        int pk[P];
+        float pv[P];
 #pragma unroll
-        for (int s = 0; s < K; ++s) {  // snapshot the partner before merging
+        for (int s = 0; s < P; ++s) {  // snapshot the partner before merging
           pk[s] = __shfl_xor(B.key[s], off);
           pv[s] = __shfl_xor(B.val[s], off);
         }
@@ -617,6 +702,7 @@ template <bool ASYNC>
 static hipError_t launch_mode(int k, const Launch &L, int grid, int merge_grid, hipStream_t s,
                               hipEvent_t b, hipEvent_t e) {
   switch (k) {
+    case 0: return launch_t<0, ASYNC>(L, grid, merge_grid, s, b, e);
     case 1: return launch_t<1, ASYNC>(L, grid, merge_grid, s, b, e);
     case 2: return launch_t<2, ASYNC>(L, grid, merge_grid, s, b, e);
     case 4: return launch_t<4, ASYNC>(L, grid, merge_grid, s, b, e);
@@ -630,6 +716,7 @@ static hipError_t launch_mode(int k, const Launch &L, int grid, int merge_grid, 
 template <bool ASYNC>
 static int occ_mode(int k) {
   switch (k) {
+    case 0: return occ_t<0, ASYNC>();
     case 1: return occ_t<1, ASYNC>();
     case 2: return occ_t<2, ASYNC>();
     case 4: return occ_t<4, ASYNC>();

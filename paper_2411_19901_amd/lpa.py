@@ -32,8 +32,12 @@ LPA_ERR_STATE = 6
 LPA_MODE_DET = 0
 LPA_MODE_ASYNC = 1
 LPA_VALIDATE = 0x100
+LPA_RULE_BM_PAPER = 0x200
 
 MODES = {"det": LPA_MODE_DET, "async": LPA_MODE_ASYNC}
+# per-vertex rule: the k-slot weighted Misra-Gries sketch, or the
+# one-candidate vote of Algorithm 3 (needs k=1)
+RULES = {"mg": 0, "bm_paper": LPA_RULE_BM_PAPER}
 
 
 class LpaGraph(ctypes.Structure):
@@ -288,7 +292,7 @@ class LPA:
     def __init__(self, row_ptr, col, weights=None, k: int = 8, tol: float = 0.05,
                  max_iter: int = 20, seed: int = 0, mode: str = "det", rho: int = 8,
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
-                 stream=None, workspace=None):
+                 stream=None, workspace=None, rule: str = "mg"):
         import torch
         for t, dt in ((row_ptr, torch.int32), (col, torch.int32)):
             if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
@@ -302,7 +306,7 @@ class LPA:
         self.max_iter = max_iter
         self.device = row_ptr.device
         cfg = lpa_config_default()
-        cfg.flags = MODES[mode] | (LPA_VALIDATE if validate else 0)
+        cfg.flags = MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
         cfg.rho = rho
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -316,6 +320,7 @@ class LPA:
             self._keep = self._keep + (workspace,)
         self.k = k
         self.mode = mode
+        self.rule = rule
         with torch.cuda.device(self.device):
             self.h = lpa_init(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr() if self.nnz else 0,
                               weights.data_ptr() if weights is not None else None, k, tol,
@@ -388,10 +393,10 @@ class LPA:
 
 
 def workspace_bytes(n: int, nnz: int, k: int = 8, max_iter: int = 20, mode: str = "det",
-                    lane_max_degree: int = 0) -> int:
+                    lane_max_degree: int = 0, rule: str = "mg") -> int:
     """Device bytes one handle needs (for LPA(..., workspace=...))."""
     cfg = lpa_config_default()
-    cfg.flags = MODES[mode] | LPA_VALIDATE
+    cfg.flags = MODES[mode] | RULES[rule] | LPA_VALIDATE
     cfg.lane_max_degree = lane_max_degree
     return lpa_workspace_bytes(n, nnz, k, max_iter, cfg)
 
@@ -401,10 +406,10 @@ class Batch:
     iteration (see lpa_batch_create in include/lpa.h)."""
 
     def __init__(self, capacity: int, k: int = 8, mode: str = "det", check_every: int = 0,
-                 stream=None, device=None):
+                 stream=None, device=None, rule: str = "mg"):
         import torch
         cfg = lpa_config_default()
-        cfg.flags = MODES[mode]
+        cfg.flags = MODES[mode] | RULES[rule]
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream

@@ -92,3 +92,22 @@ def test_batch_arguments():
     assert L.lpa_batch_create(4, 5, None, ctypes.byref(b)) == lpa.LPA_ERR_UNSUPPORTED
     assert L.lpa_batch_free(None) == lpa.LPA_OK
     assert L.lpa_batch_run(None, None, 0, None) == lpa.LPA_ERR_ARG
+
+
+def test_bm_paper_rule_flag():
+    # the vote of Algorithm 3 needs k = 1; unknown flag bits are refused
+    for mode in ("det", "async"):
+        one = lpa.workspace_bytes(5000, 80000, k=1, mode=mode, rule="bm_paper")
+        assert one == lpa.workspace_bytes(5000, 80000, k=1, mode=mode)
+    L = lpa.load()
+    out = ctypes.c_size_t(0)
+    cfg = lpa.lpa_config_default()
+    cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
+    assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG
+    assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
+    cfg.flags = lpa.LPA_MODE_DET | 0x400
+    assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+        lpa.LPA_ERR_UNSUPPORTED
+    b = ctypes.c_void_p()
+    cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
+    assert L.lpa_batch_create(4, 8, ctypes.byref(cfg), ctypes.byref(b)) == lpa.LPA_ERR_ARG

@@ -32,10 +32,10 @@ def to_dev(g):
     return rp, col, w
 
 
-def gpu_run(g, k, mode="det", tol=0.05, max_iter=20, rho=8, lane_max_degree=0):
+def gpu_run(g, k, mode="det", tol=0.05, max_iter=20, rho=8, lane_max_degree=0, rule="mg"):
     rp, col, w = to_dev(g)
     s = lpa.LPA(rp, col, w, k=k, tol=tol, max_iter=max_iter, rho=rho, mode=mode,
-                lane_max_degree=lane_max_degree)
+                lane_max_degree=lane_max_degree, rule=rule)
     it = s.run()
     labels = s.labels(device=False)
     dn, sc = s.trace()
@@ -118,7 +118,8 @@ GRAPHS = ["two-cliques-5", "two-cliques-10", "sbm1-s1", "sbm1-s2-w", "rmat12", "
 def check_det(g, k, **kw):
     labels, it, dn, sc, q = gpu_run(g, k, "det", **kw)
     tol = kw.get("tol", 0.05)
-    ref, rit, rdn, rsc = oracle.lpa_run(g.row_ptr, g.col, g.w, k=k, tol=tol,
+    ok = oracle.BM_PAPER if kw.get("rule") == "bm_paper" else k
+    ref, rit, rdn, rsc = oracle.lpa_run(g.row_ptr, g.col, g.w, k=ok, tol=tol,
                                         max_iter=kw.get("max_iter", 20), rho=kw.get("rho", 8))
     assert it == rit, (g.name, k, it, rit)
     assert np.array_equal(dn, rdn), (g.name, k, dn, rdn)
@@ -281,3 +282,68 @@ def test_async_quality_and_validity(k):
     assert abs(q - oracle.modularity(g.row_ptr, g.col, None, labels)) <= 1e-9
     if k >= 8:
         assert q > 0.9 * q_exact, (q, q_exact)
+
+
+# ---- the one-candidate vote of Algorithm 3 (LPA_RULE_BM_PAPER) ----------
+
+BM_GRAPHS = GRAPHS + ["rmat16"]
+
+
+@pytest.mark.parametrize("name", BM_GRAPHS)
+def test_bm_paper_det_parity(name):
+    if name == "rmat16" and name not in _cache:
+        _cache[name] = inputs.with_uniform_weights(inputs.rmat(16), 16)
+    check_det(graph(name), 1, rule="bm_paper")
+
+
+@pytest.mark.parametrize("lane_max", [1, 5, 64])
+def test_bm_paper_det_independent_of_bins(lane_max):
+    # lane_max 1 sends every vertex of degree > 1 through the wavefront path
+    check_det(graph("rmat14-w"), 1, rule="bm_paper", lane_max_degree=lane_max)
+
+
+def test_bm_paper_differs_from_one_slot_sketch():
+    # path 0-2-1: the vote moves vertex 2 in iteration 0, the sketch empties
+    g = inputs.from_edges(3, [(0, 2), (1, 2)], name="path021")
+    lab_bm = gpu_run(g, 1, "det", rule="bm_paper")[0]
+    lab_mg = gpu_run(g, 1, "det")[0]
+    assert lab_bm.tolist() == [1, 1, 1] and lab_mg.tolist() == [0, 1, 2]
+
+
+@pytest.mark.parametrize("lane_max", [0, 64])
+def test_bm_paper_async_validity(lane_max):
+    g = graph("rmat14-w")
+    labels, it, dn, sc, q = gpu_run(g, 1, "async", rule="bm_paper", lane_max_degree=lane_max)
+    assert 1 <= it <= 20
+    assert labels.min() >= 0 and labels.max() < g.n
+    assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, labels)) <= 1e-9
+
+
+def test_bm_paper_rejects_k():
+    rp, col, w = to_dev(graph("two-cliques-5"))
+    with pytest.raises(lpa.LpaError) as ei:
+        lpa.LPA(rp, col, w, k=8, rule="bm_paper")
+    assert ei.value.code == lpa.LPA_ERR_ARG
+
+
+def test_bm_paper_batch():
+    gs = [graph("sbm1-s1"), graph("rmat12"), graph("sbm1-s2-w"), graph("star5000")]
+    solvers = []
+    for g in gs:
+        rp, col, w = to_dev(g)
+        solvers.append(lpa.LPA(rp, col, w, k=1, rule="bm_paper"))
+    batch = lpa.Batch(len(gs), k=1, rule="bm_paper")
+    batch.run(solvers)
+    for g, s in zip(gs, solvers):
+        ref = oracle.lpa_run(g.row_ptr, g.col, g.w, k=oracle.BM_PAPER)[0]
+        assert np.array_equal(s.labels(device=False), ref), g.name
+    # a sketch handle cannot join a batch of the vote, nor the reverse
+    rp, col, w = to_dev(gs[0])
+    mg = lpa.LPA(rp, col, w, k=1)
+    with pytest.raises(lpa.LpaError):
+        batch.run([mg])
+    mg_batch = lpa.Batch(2, k=1)
+    with pytest.raises(lpa.LpaError):
+        mg_batch.run([solvers[0]])
+    for x in solvers + [mg, batch, mg_batch]:
+        x.close()
