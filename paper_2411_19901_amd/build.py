@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblpa.so")
-SOURCES = ["move.hip", "capi.hip"]
+SOURCES = ["move.hip", "modularity.hip", "capi.hip"]
 ARCH = os.environ.get("LPA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,165 @@
+// Modularity of a labelling (paper Eq. 1, community-sum form) in fp64:
+//   2m      = sum of the CSR weights,
+//   sigma   = weight of the CSR entries whose two endpoints share a label
+//             (both directions of every edge),
+//   Sigma_c = sum of K_i over the vertices labelled c,
+//   Q       = sigma / 2m - sum_c (Sigma_c / 2m)^2.
+// k_modularity accumulates 2m and sigma and scatters K_i into Sigma_c; the
+// square sum is taken by a second pass over Sigma (in capi.hip).
+//
+// Same decomposition as the move kernels: vertices above the binning
+// threshold are read by one wavefront each (coalesced), the others one lane
+// per row with the rows staged through LDS so the wavefront's loads are
+// row-contiguous.  The labels are only read, so no ordering is needed.
+#include "lpa_internal.h"
+#include "wave.h"
+
+namespace lpa {
+namespace {
+
+// tot[c] += x for every lane where `on` holds, with one atomic per distinct
+// label present in the wavefront (a converged labelling puts most vertices
+// of a wavefront in the same community).
+__device__ void add_by_label(double *tot, int c, double x, bool on) {
+  const int lane = threadIdx.x & (kWave - 1);
+  unsigned long long rest = __ballot(on);
+  while (rest) {
+    const int src = __ffsll((long long)rest) - 1;
+    const int cs = rl(c, src);
+    const bool mine = on && c == cs;
+    rest &= ~__ballot(mine);
+    const double s = wave_sum_d(mine ? x : 0.0);
+    if (lane == src) atomicAdd(&tot[cs], s);
+  }
+}
+
+// One lane per row: entries [beg, beg + len) of vertex v (v < 0: none).
+template <int T>
+__device__ void mod_lane_rows(const ModArgs &m, Stage<T> &st, int lane, int v, double &k_acc,
+                              double &in_acc) {
+  int beg = 0, len = 0, ci = -1;
+  if (v >= 0) {
+    ci = m.lab[v];
+    beg = m.row_ptr[v];
+    len = m.row_ptr[v + 1] - beg;
+  }
+  st.beg[lane] = beg;
+  st.len[lane] = len;
+  st.self[lane] = ci;
+  const int maxlen = rfl(wave_max(len));
+  wave_lds_sync();
+  double ki = 0.0, in = 0.0;
+  for (int t0 = 0; t0 < maxlen; t0 += T) {
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      const int slot = i * kWave + lane;
+      const int r = slot / T, j = slot % T;
+      const int p = t0 + j;
+      float x = 0.0f;
+      if (p < st.len[r]) {
+        const int e = st.beg[r] + p;
+        const int c = __builtin_nontemporal_load(m.col + e);
+        x = m.w ? __builtin_nontemporal_load(m.w + e) : 1.0f;
+        if (m.lab[c] == st.self[r]) in += (double)x;
+      }
+      st.w[r * (T + 1) + j] = x;
+    }
+    wave_lds_sync();
+    if (m.w) {
+#pragma unroll
+      for (int j = 0; j < T; ++j) ki += (double)st.w[lane * (T + 1) + j];
+    }
+    wave_lds_sync();
+  }
+  if (!m.w) ki = (double)len;
+  k_acc += ki;
+  in_acc += in;
+  add_by_label(m.tot, ci, ki, v >= 0 && len > 0);
+}
+
+// One wavefront per row; (pc, ps) is this wavefront's pending contribution
+// to Sigma_pc, flushed when the label changes.
+__device__ void mod_hub(const ModArgs &m, int v, double &k_acc, double &in_acc, int &pc,
+                        double &ps) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ci = m.lab[v];
+  const int rb = m.row_ptr[v], re = m.row_ptr[v + 1];
+  constexpr int U = 4;
+  double ki = 0.0, in = 0.0;
+  for (int e0 = rb; e0 < re; e0 += U * kWave) {
+    int c[U];
+    float x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kWave + lane;
+      c[u] = -1;
+      x[u] = 0.0f;
+      if (e < re) {
+        c[u] = __builtin_nontemporal_load(m.col + e);
+        x[u] = m.w ? __builtin_nontemporal_load(m.w + e) : 1.0f;
+      }
+    }
+    int l[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) l[u] = c[u] >= 0 ? m.lab[c[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ki += (double)x[u];
+      if (l[u] == ci) in += (double)x[u];
+    }
+  }
+  k_acc += ki;
+  in_acc += in;
+  const double kv = wave_sum_d(ki);
+  if (ci != pc) {
+    if (pc >= 0 && lane == 0) atomicAdd(&m.tot[pc], ps);
+    pc = ci;
+    ps = 0.0;
+  }
+  ps += kv;
+}
+
+__global__ __launch_bounds__(kBlock) void k_modularity(ModArgs m) {
+  __shared__ Stage<kStageT> stage[kBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wib = rfl(threadIdx.x / kWave);
+  const int wave = rfl(blockIdx.x * (kBlock / kWave) + wib);
+  const int nwaves = gridDim.x * (kBlock / kWave);
+  const int items = m.n_hubs + (m.n_lane + kWave - 1) / kWave;
+  double k_acc = 0.0, in_acc = 0.0, ps = 0.0;
+  int pc = -1;
+  for (int item = wave; item < items; item += nwaves) {
+    if (item < m.n_hubs) {
+      mod_hub(m, m.order[item], k_acc, in_acc, pc, ps);
+    } else {
+      const int u = (item - m.n_hubs) * kWave + lane;
+      const int v = u < m.n_lane ? m.order[m.n_hubs + u] : -1;
+      mod_lane_rows<kStageT>(m, stage[wib], lane, v, k_acc, in_acc);
+    }
+  }
+  if (pc >= 0 && lane == 0) atomicAdd(&m.tot[pc], ps);
+  k_acc = wave_sum_d(k_acc);
+  in_acc = wave_sum_d(in_acc);
+  if (lane == 0) {
+    atomicAdd(&m.acc[0], k_acc);
+    atomicAdd(&m.acc[1], in_acc);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_modularity(const ModArgs &m, int grid, hipStream_t s) {
+  if (m.n_hubs + m.n_lane > 0)
+    hipLaunchKernelGGL(k_modularity, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, s, m);
+  return hipGetLastError();
+}
+
+int modularity_blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_modularity, kBlock, 0) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace lpa

@@ -1,0 +1,56 @@
+// Wavefront helpers and the LDS row stage shared by the scan kernels
+// (lpaMove and modularity).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lpa_internal.h"
+
+namespace lpa {
+
+__device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float rfl_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ int rl(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+__device__ __forceinline__ float rl_f(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+// Order LDS accesses of this wavefront: the wavefront executes its LDS
+// instructions in order, this only keeps the compiler from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) x = max(x, __shfl_xor(x, off));
+  return x;
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+// LDS staging of 64 rows (one per lane), T entries per row per step: the
+// wavefront loads slot i * 64 + lane = entry j of row r with (r, j) =
+// (slot / T, slot % T), so its loads are row-contiguous; each lane then
+// reads its own row back.  Rows are padded to T + 1 words against bank
+// conflicts.
+template <int T>
+struct Stage {
+  int beg[kWave];
+  int len[kWave];
+  int self[kWave];
+  int lab[kWave * (T + 1)];
+  float w[kWave * (T + 1)];
+};
+
+// Entries per row per staging step (LDS per wavefront: 64 x 17 x 8 bytes).
+constexpr int kStageT = 16;
+
+}  // namespace lpa
