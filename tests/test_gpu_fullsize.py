@@ -94,3 +94,33 @@ def test_rmat24_async_modularity_parity():
     q = s.modularity()
     assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, lab)) <= 1e-9
     s.close()
+
+
+@pytest.mark.timeout(600)
+def test_grid4096_det_exact():
+    # the road-network stand-in at full size (16.8M vertices, 63.7M entries):
+    # whole det run against the oracle's whole run
+    g = inputs.grid(4096, 4096, 0.05, 0.01, seed=4096)
+    s = solver(g, k=8, mode="det")
+    it = s.run()
+    ref, rit, rdn, rsc = oracle.lpa_run(g.row_ptr, g.col, None, k=8)
+    assert it == rit
+    dn, sc = s.trace()
+    assert np.array_equal(dn, rdn) and np.array_equal(sc, rsc)
+    assert np.array_equal(s.labels(device=False), ref)
+    assert abs(s.modularity() - oracle.modularity(g.row_ptr, g.col, None, ref)) <= 1e-9
+    s.close()
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_bm_paper_det_exact():
+    # the vote of Algorithm 3 at full size, whole run against the oracle
+    g = graph(22, False)
+    s = solver(g, k=1, mode="det", rule="bm_paper")
+    it = s.run()
+    ref, rit, rdn, rsc = oracle.lpa_run(g.row_ptr, g.col, None, k=oracle.BM_PAPER)
+    assert it == rit
+    dn, sc = s.trace()
+    assert np.array_equal(dn, rdn) and np.array_equal(sc, rsc)
+    assert np.array_equal(s.labels(device=False), ref)
+    s.close()
