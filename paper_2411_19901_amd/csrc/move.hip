@@ -222,16 +222,71 @@ __device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T> &st, int
 // ---------------------------------------------------------------------------
 // LPA_MODE_DET hub path: one wavefront per vertex, CSR order.
 //
-// Lane s < K holds slot s.  The wavefront loads 64 consecutive entries
-// (lane t holds entry base + t), then every lane finds the slot whose key
-// equals its label (at most one: keys are unique).  Entries are consumed in
-// lane order: a run of entries whose label is already a key only adds
-// weights to those slots, so it is applied entry by entry with scalar lane
-// indices and no cross-lane votes; the first entry without a key takes the
-// full sketch step, after which only the lanes whose label was the replaced
-// key or is the new key change their slot.
+// The row is read in super-chunks of kHubDepth x 64 entries (lane t of
+// chunk d holds entry base + 64 d + t): the next super-chunk's column,
+// weight and label loads are in flight while the current one is consumed,
+// so the serial sketch chain is not paced by the gather latency.
 // ---------------------------------------------------------------------------
+constexpr int kHubDepth = 8;
 
+template <int D>
+struct HubChunks {
+  int lab[D];
+  float x[D];  // 0 for padding and self-loops
+
+  __device__ __forceinline__ void load(const MoveArgs &a, int v, int sb, int end, int lane) {
+    int c[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int e = sb + d * kWave + lane;
+      c[d] = -1;
+      x[d] = 0.0f;
+      if (e < end) {
+        c[d] = __builtin_nontemporal_load(a.col + e);
+        x[d] = (c[d] == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) lab[d] = c[d] >= 0 ? a.C[c[d]] : 0;
+  }
+};
+
+// Call consume(lab, x, cnt) for every 64-entry chunk of [beg, end) in order
+// (cnt = entries of the chunk; lanes >= cnt hold padding).
+template <class Consume>
+__device__ __forceinline__ void hub_feed(const MoveArgs &a, int v, int beg, int end, int lane,
+                                         Consume &&consume) {
+  // The chain of one hub bounds the whole iteration while the other
+  // wavefronts of its SIMD stream short rows: let it issue first.
+  __builtin_amdgcn_s_setprio(3);
+  HubChunks<kHubDepth> cur, nxt;
+  cur.load(a, v, beg, end, lane);
+  for (int sb = beg; sb < end; sb += kHubDepth * kWave) {
+    const int nb = sb + kHubDepth * kWave;
+    if (nb < end) nxt.load(a, v, nb, end, lane);
+#pragma unroll 1
+    for (int d = 0; d < kHubDepth; ++d) {
+      const int base = sb + d * kWave;
+      if (base >= end) break;
+      consume(cur.lab[0], cur.x[0], min(kWave, end - base));
+#pragma unroll
+      for (int q = 0; q + 1 < kHubDepth; ++q) {
+        cur.lab[q] = cur.lab[q + 1];
+        cur.x[q] = cur.x[q + 1];
+      }
+    }
+    cur = nxt;
+  }
+  __builtin_amdgcn_s_setprio(0);
+}
+
+// Lane s < K holds slot s.  For each chunk every lane first finds the slot
+// whose key equals its label (at most one: keys are unique).  Entries are
+// consumed in lane order: a run of entries whose label is already a key
+// only adds weights to those slots, so it is applied entry by entry with
+// scalar lane indices and no cross-lane votes; the first entry without a
+// key takes the full sketch step, after which only the lanes whose label
+// was the replaced key or is the new key change their slot.
 template <int K>
 __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &scanned,
                                unsigned long long &changed) {
@@ -242,28 +297,10 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
     return;
   }
   if (lane == 0) a.act_cur[v] = 0;
-  const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+  const int beg = rfl(a.row_ptr[v]), end = rfl(a.row_ptr[v + 1]);
   int key = -1;
   float val = 0.0f;
-  int e = beg + lane;
-  int nlab = 0;
-  float nw = 0.0f;
-  if (e < end) {
-    const int j = __builtin_nontemporal_load(a.col + e);
-    nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
-    nlab = a.C[j];
-  }
-  for (int base = beg; base < end; base += kWave) {
-    const int lab = nlab;
-    const float x = nw;
-    // prefetch the next 64 neighbours while this block is consumed
-    e = base + kWave + lane;
-    if (e < end) {
-      const int j = __builtin_nontemporal_load(a.col + e);
-      nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
-      nlab = a.C[j];
-    }
-    const int cnt = min(kWave, end - base);
+  hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
     int slot = -1;  // the slot holding this lane's label, if any
 #pragma unroll
     for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
@@ -278,7 +315,7 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
         run &= run - 1;
         const int sh = rl(slot, h);
         const float xh = rl_f(x, h);
-        if (lane == sh) val = val + xh;
+        val = (lane == sh) ? val + xh : val;
       }
       if (!missm) break;
       const int jm = __ffsll((long long)missm) - 1;
@@ -306,7 +343,7 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
         slot = (lab == c) ? s : slot;
       }
     }
-  }
+  });
   // heaviest live slot, ties to the lowest label; keep when empty
   int bk = cv;
   float bv = 0.0f;
@@ -329,9 +366,9 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
   scanned += (unsigned long long)(end - beg);
 }
 
-// LPA_MODE_DET hub path for the vote of Algorithm 3: the wavefront loads 64
-// consecutive entries at a time and the vote consumes them in CSR order
-// through lane reads (every lane holds the same candidate).
+// LPA_MODE_DET hub path for the vote of Algorithm 3: the vote consumes each
+// chunk in CSR order through lane reads (every lane holds the same
+// candidate).
 __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &scanned,
                                   unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -341,29 +378,12 @@ __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &
     return;
   }
   if (lane == 0) a.act_cur[v] = 0;
-  const int beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+  const int beg = rfl(a.row_ptr[v]), end = rfl(a.row_ptr[v + 1]);
   BmSketch S;
   S.clear();
-  int e = beg + lane;
-  int nlab = 0;
-  float nw = 0.0f;
-  if (e < end) {
-    const int j = __builtin_nontemporal_load(a.col + e);
-    nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
-    nlab = a.C[j];
-  }
-  for (int base = beg; base < end; base += kWave) {
-    const int lab = nlab;
-    const float x = nw;
-    e = base + kWave + lane;
-    if (e < end) {
-      const int j = __builtin_nontemporal_load(a.col + e);
-      nw = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
-      nlab = a.C[j];
-    }
-    const int cnt = min(kWave, end - base);
+  hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
     for (int t = 0; t < cnt; ++t) S.add(rl(lab, t), rl_f(x, t));
-  }
+  });
   const int c = S.max_key(cv);
   const bool moved = c != cv && (!a.pickless || c < cv);
   if (lane == 0) a.Cn[v] = moved ? c : cv;
