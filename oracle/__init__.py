@@ -54,13 +54,14 @@ def lib():
         L.orc_sketch_feed.argtypes = [ctypes.c_int, ctypes.c_int64, _i32p, _f32p, _i32p, _f32p]
         L.orc_sketch_feed.restype = None
         L.orc_lpa_move.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, ctypes.c_int, ctypes.c_int,
-                                   _i32p, _u8p, _i32p, _u8p, ctypes.c_int, _i64p]
+                                   ctypes.c_int, _i32p, _u8p, _i32p, _u8p, ctypes.c_int, _i64p]
         L.orc_lpa_move.restype = ctypes.c_int64
-        L.orc_lpa_run.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, ctypes.c_int, ctypes.c_double,
-                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i64p, _i64p]
+        L.orc_lpa_run.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p,
+                                  _i64p, _i64p]
         L.orc_lpa_run.restype = ctypes.c_int
         L.orc_lpa_choose.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, ctypes.c_int, ctypes.c_int,
-                                     _i32p, ctypes.c_int64, _i32p, _i32p, ctypes.c_int]
+                                     ctypes.c_int, _i32p, ctypes.c_int64, _i32p, _i32p, ctypes.c_int]
         L.orc_lpa_choose.restype = None
         L.orc_modularity.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, _i32p]
         L.orc_modularity.restype = ctypes.c_double
@@ -117,9 +118,9 @@ def sketch_max_key(keys, vals, keep: int) -> int:
 
 
 def lpa_run(row_ptr, col, w=None, k: int = 8, tol: float = 0.05, max_iter: int = 20,
-            rho: int = 8, nthreads: int = 0):
+            rho: int = 8, nthreads: int = 0, rescan: bool = False):
     """Algorithm 1 in Jacobi form; k=0 selects the exact argmax of Eq. 3,
-    k=BM_PAPER the vote of Algorithm 3.
+    k=BM_PAPER the vote of Algorithm 3; rescan=True the double scan.
 
     Returns (labels, iterations, dN_trace, scanned_trace)."""
     row_ptr, col, w = _csr(row_ptr, col, w)
@@ -127,14 +128,15 @@ def lpa_run(row_ptr, col, w=None, k: int = 8, tol: float = 0.05, max_iter: int =
     labels = np.empty(n, np.int32)
     dn = np.zeros(max(max_iter, 1), np.int64)
     sc = np.zeros(max(max_iter, 1), np.int64)
-    it = lib().orc_lpa_run(n, _p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, tol,
+    it = lib().orc_lpa_run(n, _p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, int(rescan), tol,
                            max_iter, rho, nthreads, _p(labels, _i32p), _p(dn, _i64p), _p(sc, _i64p))
     if it < 0:
         raise ValueError("oracle rejected its arguments")
     return labels, it, dn[:it].copy(), sc[:it].copy()
 
 
-def lpa_move(row_ptr, col, w, k: int, pickless: bool, C, act, nthreads: int = 0):
+def lpa_move(row_ptr, col, w, k: int, pickless: bool, C, act, nthreads: int = 0,
+             rescan: bool = False):
     """One Jacobi iteration from (C, act). Returns (C_next, act_next, dN, scanned)."""
     row_ptr, col, w = _csr(row_ptr, col, w)
     n = len(row_ptr) - 1
@@ -143,13 +145,15 @@ def lpa_move(row_ptr, col, w, k: int, pickless: bool, C, act, nthreads: int = 0)
     Cn = np.empty(n, np.int32)
     an = np.zeros(n, np.uint8)
     sc = np.zeros(1, np.int64)
-    dn = lib().orc_lpa_move(n, _p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, int(pickless),
+    dn = lib().orc_lpa_move(n, _p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, int(rescan),
+                            int(pickless),
                             _p(C, _i32p), _p(act, _u8p), _p(Cn, _i32p), _p(an, _u8p), nthreads,
                             _p(sc, _i64p))
     return Cn, an, int(dn), int(sc[0])
 
 
-def lpa_choose(row_ptr, col, w, k: int, pickless: bool, C, verts, nthreads: int = 0):
+def lpa_choose(row_ptr, col, w, k: int, pickless: bool, C, verts, nthreads: int = 0,
+               rescan: bool = False):
     """Label each vertex in ``verts`` would hold after one iteration from C
     (assuming it is processed)."""
     row_ptr, col, w = _csr(row_ptr, col, w)
@@ -157,7 +161,8 @@ def lpa_choose(row_ptr, col, w, k: int, pickless: bool, C, verts, nthreads: int 
     C = np.ascontiguousarray(C, dtype=np.int32)
     verts = np.ascontiguousarray(verts, dtype=np.int32)
     out = np.empty(len(verts), np.int32)
-    lib().orc_lpa_choose(n, _p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, int(pickless),
+    lib().orc_lpa_choose(n, _p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, int(rescan),
+                         int(pickless),
                          _p(C, _i32p), len(verts), _p(verts, _i32p), _p(out, _i32p), nthreads)
     return out
 

@@ -32,6 +32,11 @@
  *      strict and evaluated in double.
  *   The paper's own Boyer-Moore rule (Algorithm 3) is available as a second
  *   per-vertex rule (k == ORC_BM_PAPER), run by the same Jacobi driver.
+ *   R14 double scan (Section 4.4; Algorithm 4 rescan): the candidates are the
+ *      labels of the live slots (value > 0) after the single scan; a second
+ *      pass over the row in CSR order sums each candidate's exact weight in
+ *      fp32, and the heaviest candidate wins (ties to the lowest label; no
+ *      candidate keeps the label).
  * fp32 arithmetic is plain IEEE single precision in program order (build
  * with -ffp-contract=off and without -ffast-math).  Modularity is fp64.
  */
@@ -173,6 +178,52 @@ static int32_t choose_bm_paper(int32_t i, const int32_t *row_ptr,
   return cand;
 }
 
+/* Double scan (Section 4.4, Algorithm 4 rescan; reading R14): the single
+ * scan's live sketch labels are the candidates; their exact weights are
+ * summed in CSR order in fp32, then the heaviest wins (ties to the lowest
+ * label, none keeps). */
+static int32_t choose_rescan(int32_t i, const int32_t *row_ptr,
+                             const int32_t *col, const float *w, int k,
+                             const int32_t *C, int32_t *key, float *val) {
+  orc_sketch_clear(k, key, val);
+  for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    int32_t j = col[e];
+    if (j == i) continue;
+    orc_sketch_accumulate(k, key, val, C[j], w ? w[e] : 1.0f);
+  }
+  /* candidates: distinct labels of the live slots, with fresh sums */
+  int32_t cand[64];
+  float sum[64];
+  int nc = 0;
+  for (int s = 0; s < k; ++s) {
+    if (!(val[s] > 0.0f)) continue;
+    int dup = 0;
+    for (int q = 0; q < nc; ++q) dup |= cand[q] == key[s];
+    if (!dup) {
+      cand[nc] = key[s];
+      sum[nc] = 0.0f;
+      ++nc;
+    }
+  }
+  for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+    int32_t j = col[e];
+    if (j == i) continue;
+    for (int q = 0; q < nc; ++q)
+      if (cand[q] == C[j]) sum[q] = sum[q] + (w ? w[e] : 1.0f);
+  }
+  int32_t best = C[i];
+  float bv = 0.0f;
+  int found = 0;
+  for (int q = 0; q < nc; ++q) {
+    if (sum[q] > 0.0f && (!found || sum[q] > bv || (sum[q] == bv && cand[q] < best))) {
+      best = cand[q];
+      bv = sum[q];
+      found = 1;
+    }
+  }
+  return best;
+}
+
 /* Exact path (Eq. 3): K_{i->c} for every neighbouring label c, summed in
  * fp32 in CSR order into a dense per-thread array indexed by label (the
  * collision-free table of Section 2), then the argmax with ties to the
@@ -220,7 +271,7 @@ int orc_max_threads(void) { return resolve_threads(0); }
 /* ---------------------------------------------------------------------- */
 
 int64_t orc_lpa_move(int32_t n, const int32_t *row_ptr, const int32_t *col,
-                     const float *w, int k, int pickless, const int32_t *C,
+                     const float *w, int k, int rescan, int pickless, const int32_t *C,
                      const uint8_t *act, int32_t *C_next, uint8_t *act_next,
                      int nthreads, int64_t *scanned) {
   int64_t dN = 0, sc = 0;
@@ -242,6 +293,7 @@ int64_t orc_lpa_move(int32_t n, const int32_t *row_ptr, const int32_t *col,
       sc += row_ptr[i + 1] - row_ptr[i];
       int32_t c = (k == 0)   ? choose_exact(i, row_ptr, col, w, C, acc, touched)
                   : (k < 0) ? choose_bm_paper(i, row_ptr, col, w, C)
+                  : rescan  ? choose_rescan(i, row_ptr, col, w, k, C, key, val)
                             : choose_sketch(i, row_ptr, col, w, k, C, key, val);
       if (c != C[i] && (!pickless || c < C[i])) {
         C_next[i] = c;
@@ -264,10 +316,11 @@ int64_t orc_lpa_move(int32_t n, const int32_t *row_ptr, const int32_t *col,
 /* ---------------------------------------------------------------------- */
 
 int orc_lpa_run(int32_t n, const int32_t *row_ptr, const int32_t *col,
-                const float *w, int k, double tol, int max_iter, int rho,
+                const float *w, int k, int rescan, double tol, int max_iter, int rho,
                 int nthreads, int32_t *labels, int64_t *dN_trace,
                 int64_t *scanned_trace) {
-  if (n < 0 || (k < 0 && k != ORC_BM_PAPER) || k > 64 || max_iter < 0 || rho < 0)
+  if (n < 0 || (k < 0 && k != ORC_BM_PAPER) || k > 64 || max_iter < 0 || rho < 0 ||
+      (rescan && k <= 0))
     return -1;
   for (int32_t i = 0; i < n; ++i) labels[i] = i; /* unique initial labels */
   if (dN_trace)
@@ -285,7 +338,7 @@ int orc_lpa_run(int32_t n, const int32_t *row_ptr, const int32_t *col,
     int pickless = (rho > 0) && (l % rho == 0);
     memset(actn, 0, (size_t)n);
     int64_t sc = 0;
-    int64_t dN = orc_lpa_move(n, row_ptr, col, w, k, pickless, labels, act,
+    int64_t dN = orc_lpa_move(n, row_ptr, col, w, k, rescan, pickless, labels, act,
                               Cn, actn, nthreads, &sc);
     memcpy(labels, Cn, (size_t)n * sizeof(int32_t));
     uint8_t *t = act;
@@ -305,7 +358,7 @@ int orc_lpa_run(int32_t n, const int32_t *row_ptr, const int32_t *col,
 }
 
 void orc_lpa_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
-                    const float *w, int k, int pickless, const int32_t *C,
+                    const float *w, int k, int rescan, int pickless, const int32_t *C,
                     int64_t nv, const int32_t *verts, int32_t *out,
                     int nthreads) {
   int nt = resolve_threads(nthreads);
@@ -324,6 +377,7 @@ void orc_lpa_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
       int32_t i = verts[q];
       int32_t c = (k == 0)   ? choose_exact(i, row_ptr, col, w, C, acc, touched)
                   : (k < 0) ? choose_bm_paper(i, row_ptr, col, w, C)
+                  : rescan  ? choose_rescan(i, row_ptr, col, w, k, C, key, val)
                             : choose_sketch(i, row_ptr, col, w, k, C, key, val);
       out[q] = (c != C[i] && (!pickless || c < C[i])) ? c : C[i];
     }

@@ -46,12 +46,14 @@ int32_t orc_bm_paper_feed(int64_t len, const int32_t *labels, const float *w,
 
 /* One synchronous (Jacobi) iteration of Algorithm 1's lpaMove.
  * k >= 1: k-slot sketch; k == 0: exact argmax of Eq. 3 (dense accumulator);
- * k == ORC_BM_PAPER: the vote of Algorithm 3.
+ * k == ORC_BM_PAPER: the vote of Algorithm 3.  rescan != 0 (k >= 1 only):
+ * double scan, the sketch's live labels re-weighted exactly in a second
+ * pass over the row (Section 4.4, Algorithm 4).
  * Reads C and act, writes C_next and act_next (act_next must be zeroed by
  * the caller).  Returns the number of changed vertices; *scanned receives
  * the number of CSR entries read by the neighbourhood scans. */
 int64_t orc_lpa_move(int32_t n, const int32_t *row_ptr, const int32_t *col,
-                     const float *w, int k, int pickless, const int32_t *C,
+                     const float *w, int k, int rescan, int pickless, const int32_t *C,
                      const uint8_t *act, int32_t *C_next, uint8_t *act_next,
                      int nthreads, int64_t *scanned);
 
@@ -59,14 +61,14 @@ int64_t orc_lpa_move(int32_t n, const int32_t *row_ptr, const int32_t *col,
  * or -1 on bad arguments.  dN_trace / scanned_trace (may be NULL) receive
  * max_iter entries each. */
 int orc_lpa_run(int32_t n, const int32_t *row_ptr, const int32_t *col,
-                const float *w, int k, double tol, int max_iter, int rho,
+                const float *w, int k, int rescan, double tol, int max_iter, int rho,
                 int nthreads, int32_t *labels, int64_t *dN_trace,
                 int64_t *scanned_trace);
 
 /* The label each listed vertex would choose in one iteration, given C:
  * out[q] = chosen label of verts[q] (the current label when it keeps it). */
 void orc_lpa_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
-                    const float *w, int k, int pickless, const int32_t *C,
+                    const float *w, int k, int rescan, int pickless, const int32_t *C,
                     int64_t nv, const int32_t *verts, int32_t *out,
                     int nthreads);
 
