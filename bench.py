@@ -317,6 +317,8 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--weights", default="uniform", choices=["uniform", "unit"])
     ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--rescan", action="store_true",
+                    help="double scan: re-weight the sketch's labels exactly in a second pass")
     ap.add_argument("--rule", default="mg", choices=["mg", "bm_paper"],
                     help="per-vertex rule: k-slot Misra-Gries sketch, or the vote of "
                          "Algorithm 3 (forces k=1)")
@@ -377,7 +379,7 @@ def main():
     g, gname = build_graph(args)
     if args.rule == "bm_paper":
         args.k = 1
-    rule_tag = f"k{args.k}" if args.rule == "mg" else "bm-paper"
+    rule_tag = (f"k{args.k}" if args.rule == "mg" else "bm-paper") + ("-rescan" if args.rescan else "")
     workload = f"{gname}-{args.mode}-{rule_tag}"
 
     t = time.perf_counter()
@@ -391,6 +393,7 @@ def main():
     t = time.perf_counter()
     solver = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
                      mode=args.mode, lane_max_degree=args.lane_max_degree, rule=args.rule,
+                     rescan=args.rescan,
                      check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t) * 1e3
@@ -439,7 +442,8 @@ def main():
     achieved = kernel_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
     digest = source_digest()
     kk = args.k if args.rule == "mg" else 0  # kernel template: 0 = the vote of Algorithm 3
-    kname = f"lpa::k_move<{kk}, {'true' if args.mode == 'async' else 'false'}>"
+    kname = (f"lpa::k_move{'_rescan' if args.rescan else ''}"
+             f"<{kk}, {'true' if args.mode == 'async' else 'false'}>")
     traffic = traffic_from_profiles(kname,
                                     workload, digest)
     result = {
@@ -456,6 +460,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "n": g.n, "nnz": g.nnz, "k": args.k, "rule": args.rule,
+                   "rescan": args.rescan,
                    "mode": args.mode,
                    "tol": args.tol, "max_iter": args.max_iter, "rho": 8,
                    "step": "lpa_reset + lpa_run (all iterations to convergence)"},

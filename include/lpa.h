@@ -86,6 +86,16 @@ typedef enum lpa_status {
  * vertices into segments whose candidates are combined by the largest
  * weight, ties to the lowest label (the paper's pair-max reduction). */
 #define LPA_RULE_BM_PAPER 0x200u
+/* Double scan (Section 4.4 and Algorithm 4, "rescan"): after the single
+ * scan the labels of the sketch's non-empty slots are the candidates; a
+ * second pass over the row sums each candidate's exact weight and the
+ * heaviest candidate is chosen (ties to the lowest label; no candidate
+ * keeps the label).  In LPA_MODE_DET the second pass adds in CSR order
+ * (bit-identical to the CPU definition); in LPA_MODE_ASYNC high-degree
+ * vertices sum their segments' weights in any order.  Sketch rule only
+ * (LPA_ERR_ARG together with LPA_RULE_BM_PAPER).  Reads every processed row
+ * twice. */
+#define LPA_RESCAN 0x400u
 
 /* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji). */
 typedef struct lpa_graph {
@@ -97,7 +107,7 @@ typedef struct lpa_graph {
 
 typedef struct lpa_config {
   uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC,
-                              | LPA_VALIDATE, | LPA_RULE_BM_PAPER */
+                              | LPA_VALIDATE, | LPA_RULE_BM_PAPER, | LPA_RESCAN */
   int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per

@@ -19,6 +19,7 @@ using namespace lpa;
 namespace {
 
 constexpr int kAuxBlock = 256;
+constexpr int kPrefixArrays = 4;  // per-graph prefix sums kept for a batched launch
 
 __global__ void k_fill_i32_iota(int32_t *C, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) C[i] = i;
@@ -242,6 +243,7 @@ int grid_for(size_t count, int block = kAuxBlock, int cap = 4096) {
 struct lpa_batch {
   int capacity = 0;
   int k = 8;  // kernel selector: sketch slots, 0 = the vote of Algorithm 3
+  bool rescan = false;  // double scan (LPA_RESCAN)
   bool async_mode = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -250,7 +252,7 @@ struct lpa_batch {
   int grid_cap = 1;  // resident k_move workgroups
   void *dblock = nullptr;  // device: descriptors, prefixes, finished counter, status
   GraphDesc *d_desc = nullptr;
-  int32_t *d_prefix = nullptr;  // items[cap+1], hubs[cap+1], merge[cap+1]
+  int32_t *d_prefix = nullptr;  // items, hubs, merge items, hub segments: [cap+1] each
   int32_t *d_finished = nullptr;
   int32_t *d_status = nullptr;  // [2 * cap]
   void *hblock = nullptr;  // pinned host mirror of the same layout
@@ -261,7 +263,7 @@ struct lpa_batch {
   size_t block_bytes = 0;
   size_t off_prefix = 0, off_finished = 0, off_status = 0;
   std::vector<lpa_handle *> loaded;
-  int total_items = 0, total_hubs = 0, total_merge = 0, unfinished = 0;
+  int total_items = 0, total_hubs = 0, total_merge = 0, total_segs = 0, unfinished = 0;
   bool poisoned = false;
   std::string err;
 };
@@ -352,6 +354,7 @@ bool k_supported(int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16
 int check_k(int k, uint32_t flags) {
   if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
   if ((flags & LPA_RULE_BM_PAPER) && k != 1) return LPA_ERR_ARG;
+  if ((flags & LPA_RULE_BM_PAPER) && (flags & LPA_RESCAN)) return LPA_ERR_ARG;
   return LPA_OK;
 }
 
@@ -374,7 +377,7 @@ uint8_t *cur_flags(const lpa_handle *h) { return h->desc.act[h->iter & 1]; }
 // --- one device block per handle -------------------------------------------
 struct Layout {
   size_t st, dN, scanned, C0, C1, act0, act1, order, hist, hub_pbase, hub_act, seg_hub, pkey,
-      pval, total;
+      pval, hcand, total;
   int32_t hub_cap, seg_cap, ncls;
 };
 
@@ -410,6 +413,7 @@ Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode,
     L.seg_hub = take((size_t)L.seg_cap * 4);
     L.pkey = take((size_t)L.seg_cap * k * 4);
     L.pval = take((size_t)L.seg_cap * k * 4);
+    L.hcand = take((size_t)L.hub_cap * k * 4);
   }
   L.total = off;
   return L;
@@ -448,7 +452,7 @@ int batch_alloc(lpa_batch *b) {
   size_t off = 0;
   off = align_up(cap * sizeof(GraphDesc));
   b->off_prefix = off;
-  off = align_up(off + 3 * (cap + 1) * sizeof(int32_t));
+  off = align_up(off + kPrefixArrays * (cap + 1) * sizeof(int32_t));
   b->off_finished = off;
   off = align_up(off + sizeof(int32_t));
   b->off_status = off;
@@ -476,7 +480,7 @@ int batch_alloc(lpa_batch *b) {
   b->device = dev;
   if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return LPA_ERR_HIP;
-  b->grid_cap = b->cus * move_blocks_per_cu(b->k, b->async_mode);
+  b->grid_cap = b->cus * move_blocks_per_cu(b->k, b->async_mode, b->rescan);
   return LPA_OK;
 }
 
@@ -494,15 +498,15 @@ int move_items(const lpa_handle *h) { return h->desc.items; }
 int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
   if (count < 0 || count > b->capacity) return LPA_ERR_ARG;
   int32_t *pi = b->h_prefix, *ph = b->h_prefix + (b->capacity + 1),
-          *pm = b->h_prefix + 2 * (b->capacity + 1);
-  pi[0] = ph[0] = pm[0] = 0;
+          *pm = b->h_prefix + 2 * (b->capacity + 1), *ps = b->h_prefix + 3 * (b->capacity + 1);
+  pi[0] = ph[0] = pm[0] = ps[0] = 0;
   int unfinished = 0;
   for (int g = 0; g < count; ++g) {
     lpa_handle *h = hs[g];
     if (!h) return LPA_ERR_ARG;
     if (h->poisoned) return LPA_ERR_HIP;
-    if (kernel_k(h->k, h->flags) != b->k || h->async_mode != b->async_mode || h->device != b->device ||
-        h->stream != b->stream)
+    if (kernel_k(h->k, h->flags) != b->k || ((h->flags & LPA_RESCAN) != 0) != b->rescan ||
+        h->async_mode != b->async_mode || h->device != b->device || h->stream != b->stream)
       return LPA_ERR_ARG;
     for (int q = 0; q < g; ++q)
       if (hs[q] == h) return LPA_ERR_ARG;
@@ -512,16 +516,19 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
     pi[g + 1] = pi[g] + (live ? move_items(h) : 0);
     ph[g + 1] = ph[g] + (live && b->async_mode ? h->desc.n_hubs : 0);
     pm[g + 1] = pm[g] + (live && b->async_mode ? (h->desc.n_hubs + kWave - 1) / kWave : 0);
+    ps[g + 1] = ps[g] + (live && b->async_mode ? h->desc.n_seg : 0);
   }
   // pad the prefixes to the table capacity so the three arrays keep their offsets
   b->total_items = pi[count];
   b->total_hubs = ph[count];
   b->total_merge = pm[count];
+  b->total_segs = ps[count];
   b->unfinished = unfinished;
   b->loaded.assign(hs, hs + count);
   HIP_TRY_B(b, hipMemcpyAsync(b->d_desc, b->h_desc, (size_t)count * sizeof(GraphDesc),
                               hipMemcpyHostToDevice, b->stream));
-  HIP_TRY_B(b, hipMemcpyAsync(b->d_prefix, b->h_prefix, 3 * (b->capacity + 1) * sizeof(int32_t),
+  HIP_TRY_B(b, hipMemcpyAsync(b->d_prefix, b->h_prefix,
+                              kPrefixArrays * (b->capacity + 1) * sizeof(int32_t),
                               hipMemcpyHostToDevice, b->stream));
   return LPA_OK;
 }
@@ -532,10 +539,12 @@ Launch make_launch(lpa_batch *b) {
   L.prefix_items = b->d_prefix;
   L.prefix_hubs = b->d_prefix + (b->capacity + 1);
   L.prefix_merge = b->d_prefix + 2 * (b->capacity + 1);
+  L.prefix_segs = b->d_prefix + 3 * (b->capacity + 1);
   L.G = (int32_t)b->loaded.size();
   L.total_items = b->total_items;
   L.total_hubs = b->total_hubs;
   L.total_merge = b->total_merge;
+  L.total_segs = b->total_segs;
   L.finished = b->d_finished;
   L.status_out = b->d_status;
   return L;
@@ -581,7 +590,8 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
         ee = prof->ev_end[l];
       }
     }
-    hipError_t e = launch_iteration(b->k, b->async_mode, L, grid, mg, b->stream, eb, ee);
+    hipError_t e =
+        launch_iteration(b->k, b->async_mode, b->rescan, L, grid, mg, b->stream, eb, ee);
     if (e != hipSuccess) return fail_hip_b(b, e, "iteration launch");
     if (b->check_every > 0 && (i + 1) % b->check_every == 0 && i + 1 < iters) {
       HIP_TRY_B(b, hipMemcpyAsync(b->h_finished, b->d_finished, sizeof(int32_t),
@@ -646,7 +656,7 @@ static int check_config(const lpa_config &cfg) {
     return LPA_ERR_ARG;
   const uint32_t mode = cfg.flags & LPA_MODE_MASK;
   if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
-  if ((cfg.flags & ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER)) != 0)
+  if ((cfg.flags & ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN)) != 0)
     return LPA_ERR_UNSUPPORTED;
   if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
   return LPA_OK;
@@ -767,6 +777,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     d.seg_hub = (const int32_t *)(base + Ly.seg_hub);
     d.part_key = (int32_t *)(base + Ly.pkey);
     d.part_val = (float *)(base + Ly.pval);
+    d.hub_cand = (int32_t *)(base + Ly.hcand);
   }
 
   hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, 0, 0);
@@ -832,6 +843,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   if (!h->self) return bail(LPA_ERR_NOMEM);
   h->self->capacity = 1;
   h->self->k = kernel_k(k, cfg.flags);
+  h->self->rescan = (cfg.flags & LPA_RESCAN) != 0;
   h->self->async_mode = h->async_mode;
   h->self->stream = h->stream;
   h->self->check_every = h->check_every;
@@ -900,6 +912,7 @@ int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **
   if (!b) return LPA_ERR_NOMEM;
   b->capacity = capacity;
   b->k = kernel_k(k, cfg.flags);
+  b->rescan = (cfg.flags & LPA_RESCAN) != 0;
   b->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   b->stream = (hipStream_t)cfg.stream;
   b->check_every = cfg.check_every;

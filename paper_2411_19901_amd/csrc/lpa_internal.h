@@ -58,22 +58,26 @@ struct GraphDesc {
   uint8_t *hub_act;          // [n_hubs] flags snapshot of this iteration
   int32_t *part_key;         // [n_seg * k]
   float *part_val;           // [n_seg * k]
+  int32_t *hub_cand;         // [n_hubs * k] double-scan candidates (-1: none)
   unsigned long long *dN;       // [max_iter] changed vertices per iteration
   unsigned long long *scanned;  // [max_iter] CSR entries scanned per iteration
   GraphStatus *st;
 };
 
 // One set of launches over many graphs.  prefix_* hold G + 1 exclusive
-// prefix sums of the per-graph counts (move items, hubs, merge items).
+// prefix sums of the per-graph counts (move items, hubs, merge items, hub
+// segments).
 struct Launch {
   const GraphDesc *d;
   const int32_t *prefix_items;
   const int32_t *prefix_hubs;
   const int32_t *prefix_merge;
+  const int32_t *prefix_segs;  // hub segments (double scan in LPA_MODE_ASYNC)
   int32_t G;
   int32_t total_items;
   int32_t total_hubs;
   int32_t total_merge;
+  int32_t total_segs;
   int32_t *finished;        // graphs that have finished (counter)
   int32_t *status_out;      // [2 * G]: iter, done of every graph after the launch
 };
@@ -103,13 +107,15 @@ struct MoveArgs {
 };
 
 // Kernel selector: k slots of the weighted Misra-Gries sketch, or 0 for the
-// one-candidate vote of Algorithm 3 (LPA_RULE_BM_PAPER).
+// one-candidate vote of Algorithm 3 (LPA_RULE_BM_PAPER); rescan selects
+// the double scan (LPA_RESCAN, k > 0 only).
 // Enqueue one iteration of every graph in the launch (async: hub flag
-// snapshot, k_move, hub merge; det: k_move; then the convergence test).
-// Non-null events are recorded around k_move only.
-hipError_t launch_iteration(int k, bool async_mode, const Launch &L, int grid, int merge_grid,
-                            hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
-int move_blocks_per_cu(int k, bool async_mode);
+// snapshot, k_move, hub merge, and for the double scan the hub re-weighting
+// and decision; det: k_move; then the convergence test).  Non-null events
+// are recorded around k_move only.
+hipError_t launch_iteration(int k, bool async_mode, bool rescan, const Launch &L, int grid,
+                            int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
+int move_blocks_per_cu(int k, bool async_mode, bool rescan);
 
 // Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read
 // by one wavefront each, order[n_hubs, n_hubs + n_lane) one lane each.

@@ -156,9 +156,9 @@ constexpr int slots_of(int K) { return K == 0 ? 1 : K; }
 
 // Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
 // nothing).  All lanes of the wavefront must call it together.
-template <class SK, int T>
-__device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T> &st, int lane, int beg,
-                                            int len, int self, SK &S) {
+template <int T, class Feed>
+__device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T> &st, int lane, int beg,
+                                            int len, int self, Feed &&feed) {
   st.beg[lane] = beg;
   st.len[lane] = len;
   st.self[lane] = self;
@@ -184,14 +184,55 @@ __device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T> &st, int
     }
     wave_lds_sync();
     // columns past the longest row of the wavefront hold only padding
-    // (weight 0, a no-op), so the uniform bound tn skips them
+    // (label -1, weight 0), so the uniform bound tn skips them
     const int tn = min(T, maxlen - t0);
 #pragma unroll
     for (int j = 0; j < T; ++j)
-      if (j < tn) S.add(st.lab[lane * (T + 1) + j], st.w[lane * (T + 1) + j]);
+      if (j < tn) feed(st.lab[lane * (T + 1) + j], st.w[lane * (T + 1) + j]);
     wave_lds_sync();
   }
 }
+
+// Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
+// nothing).  All lanes of the wavefront must call it together.
+template <class SK, int T>
+__device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T> &st, int lane, int beg,
+                                            int len, int self, SK &S) {
+  staged_rows<T>(a, st, lane, beg, len, self, [&](int lab, float x) { S.add(lab, x); });
+}
+
+// Double scan (Section 4.4, Algorithm 4 rescan): the live slots of the
+// single scan's sketch are the candidates; a second pass in CSR order sums
+// each candidate's exact weight, and the heaviest wins (ties to the lowest
+// label; no candidate keeps `keep`).
+template <int K>
+struct Rescan {
+  int key[K];  // candidate labels, -1 for slots that were empty
+  float acc[K];
+
+  __device__ __forceinline__ void from(const LaneSketch<K> &S) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      key[s] = S.val[s] > 0.0f ? S.key[s] : -1;
+      acc[s] = 0.0f;
+    }
+  }
+  __device__ __forceinline__ void add(int c, float x) {
+#pragma unroll
+    for (int s = 0; s < K; ++s) acc[s] = (c >= 0 && key[s] == c) ? acc[s] + x : acc[s];
+  }
+  __device__ __forceinline__ int best(int keep) const {
+    int bk = keep;
+    float bv = 0.0f;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const bool better = acc[s] > bv || (acc[s] == bv && acc[s] > 0.0f && key[s] < bk);
+      bk = better ? key[s] : bk;
+      bv = better ? acc[s] : bv;
+    }
+    return bk;
+  }
+};
 
 // Flag a neighbour of a changed vertex as unprocessed (plain byte store:
 // reading the flag first to skip repeated marks measured slower).
@@ -287,7 +328,7 @@ __device__ __forceinline__ void hub_feed(const MoveArgs &a, int v, int beg, int 
 // scalar lane indices and no cross-lane votes; the first entry without a
 // key takes the full sketch step, after which only the lanes whose label
 // was the replaced key or is the new key change their slot.
-template <int K>
+template <int K, bool RS>
 __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &scanned,
                                unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -344,6 +385,25 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
       }
     }
   });
+  if constexpr (RS) {
+    // double scan: the live slots' labels are re-weighted exactly, each
+    // slot's entries added in CSR order by the slot's lane
+    key = val > 0.0f ? key : -1;
+    val = 0.0f;
+    hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
+      int slot = -1;
+#pragma unroll
+      for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
+      unsigned long long pend = __ballot(slot >= 0 && lane < cnt && x > 0.0f);
+      while (pend) {
+        const int h = __ffsll((long long)pend) - 1;
+        pend &= pend - 1;
+        const int sh = rl(slot, h);
+        const float xh = rl_f(x, h);
+        val = (lane == sh) ? val + xh : val;
+      }
+    });
+  }
   // heaviest live slot, ties to the lowest label; keep when empty
   int bk = cv;
   float bv = 0.0f;
@@ -399,7 +459,7 @@ __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &
 // hub h = seg_hub[u] (async only); otherwise whole vertex order[n_hubs + u -
 // n_seg].
 // ---------------------------------------------------------------------------
-template <int K, bool ASYNC>
+template <int K, bool ASYNC, bool RS>
 __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st, int u,
                                            unsigned long long &scanned,
                                            unsigned long long &changed) {
@@ -431,6 +491,18 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st
   S.clear();
   staged_scan<typename SketchOf<K>::type, kStageT>(a, st, lane, beg, len, v, S);
   scanned += (unsigned long long)len;
+  int c = cv;
+  if constexpr (RS) {
+    // second pass over whole rows only: hub segments are re-weighted after
+    // their sketches are merged (k_hub_rescan)
+    Rescan<K> R;
+    R.from(S);
+    staged_rows<kStageT>(a, st, lane, beg, whole ? len : 0, v,
+                         [&](int lab, float x) { R.add(lab, x); });
+    if (whole) c = R.best(cv);
+  } else {
+    if (whole) c = S.max_key(cv);
+  }
   bool moved = false;
   if (pslot >= 0) {
     if (active) {  // partial sketch of one hub segment
@@ -442,7 +514,6 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st
       }
     }
   } else if (whole) {
-    const int c = S.max_key(cv);
     moved = active && c != cv && (!a.pickless || c < cv);
     if (ASYNC) {
       if (moved) a.C[v] = c;
@@ -512,8 +583,8 @@ __device__ __forceinline__ void flush_counts(unsigned long long *dN, unsigned lo
   scanned_lane = scanned_w = changed_w = 0;
 }
 
-template <int K, bool ASYNC>
-__global__ __launch_bounds__(kBlock) void k_move(Launch L) {
+template <int K, bool ASYNC, bool RS>
+__device__ __forceinline__ void move_body(const Launch &L) {
   __shared__ Stage<kStageT> stage[kBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = rfl(threadIdx.x / kWave);
@@ -540,12 +611,24 @@ __global__ __launch_bounds__(kBlock) void k_move(Launch L) {
       if constexpr (K == 0)
         hub_vertex_det_bm(a, a.order[local], scanned_w, changed_w);
       else
-        hub_vertex_det<K>(a, a.order[local], scanned_w, changed_w);
+        hub_vertex_det<K, RS>(a, a.order[local], scanned_w, changed_w);
     } else
-      lane_units<K, ASYNC>(a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane,
-                           changed_w);
+      lane_units<K, ASYNC, RS>(a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane,
+                               changed_w);
   }
   flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
+}
+
+// One iteration's label moves (single scan) ...
+template <int K, bool ASYNC>
+__global__ __launch_bounds__(kBlock) void k_move(Launch L) {
+  move_body<K, ASYNC, false>(L);
+}
+
+// ... and with the double scan (LPA_RESCAN; sketch rule only).
+template <int K, bool ASYNC>
+__global__ __launch_bounds__(kBlock) void k_move_rescan(Launch L) {
+  move_body<K, ASYNC, true>(L);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,19 +650,36 @@ __global__ void k_hub_snapshot(Launch L) {
   }
 }
 
-// Merge the partial sketches of every active hub (Section 4.3) and update
-// its label.  A wavefront takes 64 hubs of one graph: hubs with at most 64
-// partials are merged by one lane each; larger ones by the whole wavefront
-// (lane l merges partials l, l + 64, ..., then a pairwise exchange across
-// lanes).
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
+// A moved hub marks its neighbours, row-contiguous, one hub at a time
+// (all lanes call it together; `moved` and `v` are per lane).
+__device__ __forceinline__ void mark_moved_hubs(const MoveArgs &a, bool moved, int v, int lane) {
+  unsigned long long rest = __ballot(moved);
+  while (rest) {
+    const int src = __ffsll((long long)rest) - 1;
+    rest &= rest - 1;
+    const int bv = __shfl(v, src);
+    const int rb = a.row_ptr[bv], re = a.row_ptr[bv + 1];
+    for (int e = rb + lane; e < re; e += kWave) mark(a, __builtin_nontemporal_load(a.col + e));
+  }
+}
+
+// Merge the partial sketches of every active hub (Section 4.3).  A wavefront
+// takes 64 hubs of one graph: hubs with at most 64 partials are merged by
+// one lane each; larger ones by the whole wavefront (lane l merges partials
+// l, l + 64, ..., then a pairwise exchange across lanes).  RS = false: the
+// hub takes the merged sketch's heaviest label.  RS = true (double scan):
+// the merged sketch's live labels are stored as the hub's candidates for
+// k_hub_rescan / k_hub_pick.
+template <int K, bool RS>
+__device__ __forceinline__ void hub_merge_body(const Launch &L) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = rfl((blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int nwaves = gridDim.x * (kBlock / kWave);
   unsigned long long changed_w = 0, zero_lane = 0, zero_w = 0;
   int cur = -1;
   unsigned long long *cdN = nullptr;
+  using SK = typename SketchOf<K>::type;
+  constexpr int P = slots_of(K);
   for (int item = wave; item < L.total_merge; item += nwaves) {
     const int g = rfl(find_graph(L.prefix_merge, L.G, item));
     const GraphDesc &gd = L.d[g];
@@ -601,8 +701,6 @@ __global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
       np = a.hub_pbase[h + 1] - p0;
       cv = a.C[v];
     }
-    using SK = typename SketchOf<K>::type;
-    constexpr int P = slots_of(K);
     int c = cv;
     const bool small = active && np <= kWave;
     SK S;
@@ -618,7 +716,12 @@ __global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
         }
         S.merge_from(pk, pv);
       }
-      c = S.max_key(cv);
+      if constexpr (RS) {
+#pragma unroll
+        for (int s = 0; s < P; ++s) gd.hub_cand[(size_t)h * P + s] = S.val[s] > 0.0f ? S.key[s] : -1;
+      } else {
+        c = S.max_key(cv);
+      }
     }
     unsigned long long big = __ballot(active && !small);
     while (big) {
@@ -648,21 +751,169 @@ __global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
         }
         B.merge_from(pk, pv);
       }
-      const int bc = rfl(B.max_key(bcv));
-      if (lane == src) c = bc;
+      if constexpr (RS) {
+        const int bh = (item - L.prefix_merge[g]) * kWave + src;
+        if (lane == 0) {
+#pragma unroll
+          for (int s = 0; s < P; ++s)
+            gd.hub_cand[(size_t)bh * P + s] = B.val[s] > 0.0f ? B.key[s] : -1;
+        }
+      } else {
+        const int bc = rfl(B.max_key(bcv));
+        if (lane == src) c = bc;
+      }
+    }
+    if constexpr (!RS) {
+      const bool moved = active && c != cv && (!a.pickless || c < cv);
+      if (moved) a.C[v] = c;
+      changed_w += (unsigned long long)__popcll(__ballot(moved));
+      mark_moved_hubs(a, moved, v, lane);
+    }
+  }
+  flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hub_merge(Launch L) {
+  hub_merge_body<K, false>(L);
+}
+
+// Double scan, hub candidates: merge the partial sketches into candidates.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hub_cand(Launch L) {
+  hub_merge_body<K, true>(L);
+}
+
+// Double scan, hub re-weighting: one wavefront per hub segment sums the
+// exact weight of each of its hub's candidates over the segment's entries
+// (any order: LPA_MODE_ASYNC only) into the segment's partial values.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = rfl((blockIdx.x * kBlock + threadIdx.x) / kWave);
+  const int nwaves = gridDim.x * (kBlock / kWave);
+  for (int item = wave; item < L.total_segs; item += nwaves) {
+    const int g = rfl(find_graph(L.prefix_segs, L.G, item));
+    const GraphDesc &gd = L.d[g];
+    if (gd.st->done) continue;
+    const MoveArgs a = make_args(gd, gd.st->iter);
+    const int u = item - L.prefix_segs[g];
+    const int h = a.seg_hub[u];
+    if (a.hub_act[h] == 0) continue;
+    const int v = a.order[h];
+    const int q = u - a.hub_pbase[h];
+    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
+    const int beg = rb + q * a.seg_len, end = min(beg + a.seg_len, re);
+    int cand[K];
+    float acc[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      cand[s] = gd.hub_cand[(size_t)h * K + s];
+      acc[s] = 0.0f;
+    }
+    constexpr int U = 4;
+    for (int e0 = beg; e0 < end; e0 += U * kWave) {
+      int lab[U];
+      float x[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const int e = e0 + t * kWave + lane;
+        lab[t] = -1;
+        x[t] = 0.0f;
+        if (e < end) {
+          const int j = __builtin_nontemporal_load(a.col + e);
+          x[t] = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
+          lab[t] = a.C[j];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < U; ++t)
+#pragma unroll
+        for (int s = 0; s < K; ++s)
+          acc[s] = (lab[t] >= 0 && lab[t] == cand[s]) ? acc[s] + x[t] : acc[s];
+    }
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+      for (int off = kWave / 2; off >= 1; off >>= 1) acc[s] += __shfl_xor(acc[s], off);
+      if (lane == 0) a.part_val[(size_t)u * K + s] = acc[s];
+    }
+  }
+}
+
+// Double scan, hub decision: add up the segments' candidate weights, take
+// the heaviest candidate (ties to the lowest label), update the label and
+// flag the neighbours.  Same hub-to-lane layout as k_hub_merge.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = rfl((blockIdx.x * kBlock + threadIdx.x) / kWave);
+  const int nwaves = gridDim.x * (kBlock / kWave);
+  unsigned long long changed_w = 0, zero_lane = 0, zero_w = 0;
+  int cur = -1;
+  unsigned long long *cdN = nullptr;
+  for (int item = wave; item < L.total_merge; item += nwaves) {
+    const int g = rfl(find_graph(L.prefix_merge, L.G, item));
+    const GraphDesc &gd = L.d[g];
+    if (gd.st->done) continue;
+    const int iter = gd.st->iter;
+    if (g != cur) {
+      flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
+      cur = g;
+      cdN = gd.dN + iter;
+    }
+    const MoveArgs a = make_args(gd, iter);
+    const int h = (item - L.prefix_merge[g]) * kWave + lane;
+    int v = -1, p0 = 0, np = 0, cv = 0;
+    bool active = false;
+    if (h < a.n_hubs) {
+      v = a.order[h];
+      active = a.hub_act[h] != 0;
+      p0 = a.hub_pbase[h];
+      np = a.hub_pbase[h + 1] - p0;
+      cv = a.C[v];
+    }
+    float tot[K];
+#pragma unroll
+    for (int s = 0; s < K; ++s) tot[s] = 0.0f;
+    const bool small = active && np <= kWave;
+    if (small)
+      for (int p = p0; p < p0 + np; ++p)
+#pragma unroll
+        for (int s = 0; s < K; ++s) tot[s] += a.part_val[(size_t)p * K + s];
+    unsigned long long big = __ballot(active && !small);
+    while (big) {
+      const int src = __ffsll((long long)big) - 1;
+      big &= big - 1;
+      const int bp0 = __shfl(p0, src), bnp = __shfl(np, src);
+      float t[K];
+#pragma unroll
+      for (int s = 0; s < K; ++s) t[s] = 0.0f;
+      for (int p = bp0 + lane; p < bp0 + bnp; p += kWave)
+#pragma unroll
+        for (int s = 0; s < K; ++s) t[s] += a.part_val[(size_t)p * K + s];
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int off = kWave / 2; off >= 1; off >>= 1) t[s] += __shfl_xor(t[s], off);
+        tot[s] = (lane == src) ? t[s] : tot[s];
+      }
+    }
+    int c = cv;
+    if (active) {
+      float bv = 0.0f;
+#pragma unroll
+      for (int s = 0; s < K; ++s) {
+        const int ks = gd.hub_cand[(size_t)h * K + s];
+        const bool better = ks >= 0 && (tot[s] > bv || (tot[s] == bv && tot[s] > 0.0f && ks < c));
+        c = better ? ks : c;
+        bv = better ? tot[s] : bv;
+      }
     }
     const bool moved = active && c != cv && (!a.pickless || c < cv);
     if (moved) a.C[v] = c;
-    const unsigned long long mv = __ballot(moved);
-    changed_w += (unsigned long long)__popcll(mv);
-    unsigned long long rest = mv;
-    while (rest) {  // every moved hub marks its neighbours, row-contiguous
-      const int src = __ffsll((long long)rest) - 1;
-      rest &= rest - 1;
-      const int bv = __shfl(v, src);
-      const int rb = a.row_ptr[bv], re = a.row_ptr[bv + 1];
-      for (int e = rb + lane; e < re; e += kWave) mark(a, __builtin_nontemporal_load(a.col + e));
-    }
+    changed_w += (unsigned long long)__popcll(__ballot(moved));
+    mark_moved_hubs(a, moved, v, lane);
   }
   flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
 }
@@ -691,7 +942,7 @@ __global__ void k_finish(Launch L) {
 }
 
 // ---------------------------------------------------------------------------
-template <int K, bool ASYNC>
+template <int K, bool ASYNC, bool RS>
 static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_t s,
                            hipEvent_t ev_beg, hipEvent_t ev_end) {
   hipError_t e = hipSuccess;
@@ -700,61 +951,85 @@ static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_
     hipLaunchKernelGGL(k_hub_snapshot, dim3(sg), dim3(256), 0, s, L);
   }
   if (ev_beg && (e = hipEventRecord(ev_beg, s)) != hipSuccess) return e;
-  if (L.total_items > 0) hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, L);
+  if (L.total_items > 0) {
+    if constexpr (RS)
+      hipLaunchKernelGGL((k_move_rescan<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, L);
+    else
+      hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, L);
+  }
   if (ev_end && (e = hipEventRecord(ev_end, s)) != hipSuccess) return e;
-  if (ASYNC && L.total_merge > 0)
-    hipLaunchKernelGGL((k_hub_merge<K>), dim3(merge_grid), dim3(kBlock), 0, s, L);
+  if (ASYNC && L.total_merge > 0) {
+    if constexpr (RS) {
+      hipLaunchKernelGGL((k_hub_cand<K>), dim3(merge_grid), dim3(kBlock), 0, s, L);
+      if (L.total_segs > 0)
+        hipLaunchKernelGGL((k_hub_rescan<K>), dim3(grid), dim3(kBlock), 0, s, L);
+      hipLaunchKernelGGL((k_hub_pick<K>), dim3(merge_grid), dim3(kBlock), 0, s, L);
+    } else {
+      hipLaunchKernelGGL((k_hub_merge<K>), dim3(merge_grid), dim3(kBlock), 0, s, L);
+    }
+  }
   const int fg = (L.G + 255) / 256 < 64 ? (L.G + 255) / 256 : 64;
   hipLaunchKernelGGL(k_finish, dim3(fg > 0 ? fg : 1), dim3(256), 0, s, L);
   return hipGetLastError();
 }
 
-template <int K, bool ASYNC>
+template <int K, bool ASYNC, bool RS>
 static int occ_t() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)k_move<K, ASYNC>, kBlock, 0) !=
-      hipSuccess)
-    return 1;
+  const void *f;
+  if constexpr (RS)
+    f = (const void *)k_move_rescan<K, ASYNC>;
+  else
+    f = (const void *)k_move<K, ASYNC>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
-template <bool ASYNC>
+template <bool ASYNC, bool RS>
 static hipError_t launch_mode(int k, const Launch &L, int grid, int merge_grid, hipStream_t s,
                               hipEvent_t b, hipEvent_t e) {
   switch (k) {
-    case 0: return launch_t<0, ASYNC>(L, grid, merge_grid, s, b, e);
-    case 1: return launch_t<1, ASYNC>(L, grid, merge_grid, s, b, e);
-    case 2: return launch_t<2, ASYNC>(L, grid, merge_grid, s, b, e);
-    case 4: return launch_t<4, ASYNC>(L, grid, merge_grid, s, b, e);
-    case 8: return launch_t<8, ASYNC>(L, grid, merge_grid, s, b, e);
-    case 16: return launch_t<16, ASYNC>(L, grid, merge_grid, s, b, e);
-    case 32: return launch_t<32, ASYNC>(L, grid, merge_grid, s, b, e);
+    case 1: return launch_t<1, ASYNC, RS>(L, grid, merge_grid, s, b, e);
+    case 2: return launch_t<2, ASYNC, RS>(L, grid, merge_grid, s, b, e);
+    case 4: return launch_t<4, ASYNC, RS>(L, grid, merge_grid, s, b, e);
+    case 8: return launch_t<8, ASYNC, RS>(L, grid, merge_grid, s, b, e);
+    case 16: return launch_t<16, ASYNC, RS>(L, grid, merge_grid, s, b, e);
+    case 32: return launch_t<32, ASYNC, RS>(L, grid, merge_grid, s, b, e);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <bool ASYNC>
+template <bool ASYNC, bool RS>
 static int occ_mode(int k) {
   switch (k) {
-    case 0: return occ_t<0, ASYNC>();
-    case 1: return occ_t<1, ASYNC>();
-    case 2: return occ_t<2, ASYNC>();
-    case 4: return occ_t<4, ASYNC>();
-    case 8: return occ_t<8, ASYNC>();
-    case 16: return occ_t<16, ASYNC>();
-    case 32: return occ_t<32, ASYNC>();
+    case 1: return occ_t<1, ASYNC, RS>();
+    case 2: return occ_t<2, ASYNC, RS>();
+    case 4: return occ_t<4, ASYNC, RS>();
+    case 8: return occ_t<8, ASYNC, RS>();
+    case 16: return occ_t<16, ASYNC, RS>();
+    case 32: return occ_t<32, ASYNC, RS>();
     default: return 1;
   }
 }
 
-hipError_t launch_iteration(int k, bool async_mode, const Launch &L, int grid, int merge_grid,
-                            hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
-  return async_mode ? launch_mode<true>(k, L, grid, merge_grid, s, ev_beg, ev_end)
-                    : launch_mode<false>(k, L, grid, merge_grid, s, ev_beg, ev_end);
+hipError_t launch_iteration(int k, bool async_mode, bool rescan, const Launch &L, int grid,
+                            int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
+  if (k == 0) {  // the vote of Algorithm 3 (no double scan)
+    if (rescan) return hipErrorInvalidValue;
+    return async_mode ? launch_t<0, true, false>(L, grid, merge_grid, s, ev_beg, ev_end)
+                      : launch_t<0, false, false>(L, grid, merge_grid, s, ev_beg, ev_end);
+  }
+  if (rescan)
+    return async_mode ? launch_mode<true, true>(k, L, grid, merge_grid, s, ev_beg, ev_end)
+                      : launch_mode<false, true>(k, L, grid, merge_grid, s, ev_beg, ev_end);
+  return async_mode ? launch_mode<true, false>(k, L, grid, merge_grid, s, ev_beg, ev_end)
+                    : launch_mode<false, false>(k, L, grid, merge_grid, s, ev_beg, ev_end);
 }
 
-int move_blocks_per_cu(int k, bool async_mode) {
-  return async_mode ? occ_mode<true>(k) : occ_mode<false>(k);
+int move_blocks_per_cu(int k, bool async_mode, bool rescan) {
+  if (k == 0) return async_mode ? occ_t<0, true, false>() : occ_t<0, false, false>();
+  if (rescan) return async_mode ? occ_mode<true, true>(k) : occ_mode<false, true>(k);
+  return async_mode ? occ_mode<true, false>(k) : occ_mode<false, false>(k);
 }
 
 }  // namespace lpa

@@ -33,6 +33,7 @@ LPA_MODE_DET = 0
 LPA_MODE_ASYNC = 1
 LPA_VALIDATE = 0x100
 LPA_RULE_BM_PAPER = 0x200
+LPA_RESCAN = 0x400
 
 MODES = {"det": LPA_MODE_DET, "async": LPA_MODE_ASYNC}
 # per-vertex rule: the k-slot weighted Misra-Gries sketch, or the
@@ -292,7 +293,7 @@ class LPA:
     def __init__(self, row_ptr, col, weights=None, k: int = 8, tol: float = 0.05,
                  max_iter: int = 20, seed: int = 0, mode: str = "det", rho: int = 8,
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
-                 stream=None, workspace=None, rule: str = "mg"):
+                 stream=None, workspace=None, rule: str = "mg", rescan: bool = False):
         import torch
         for t, dt in ((row_ptr, torch.int32), (col, torch.int32)):
             if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
@@ -306,7 +307,8 @@ class LPA:
         self.max_iter = max_iter
         self.device = row_ptr.device
         cfg = lpa_config_default()
-        cfg.flags = MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
+        cfg.flags = (MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
+                     | (LPA_RESCAN if rescan else 0))
         cfg.rho = rho
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -321,6 +323,7 @@ class LPA:
         self.k = k
         self.mode = mode
         self.rule = rule
+        self.rescan = rescan
         with torch.cuda.device(self.device):
             self.h = lpa_init(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr() if self.nnz else 0,
                               weights.data_ptr() if weights is not None else None, k, tol,
@@ -393,10 +396,10 @@ class LPA:
 
 
 def workspace_bytes(n: int, nnz: int, k: int = 8, max_iter: int = 20, mode: str = "det",
-                    lane_max_degree: int = 0, rule: str = "mg") -> int:
+                    lane_max_degree: int = 0, rule: str = "mg", rescan: bool = False) -> int:
     """Device bytes one handle needs (for LPA(..., workspace=...))."""
     cfg = lpa_config_default()
-    cfg.flags = MODES[mode] | RULES[rule] | LPA_VALIDATE
+    cfg.flags = MODES[mode] | RULES[rule] | LPA_VALIDATE | (LPA_RESCAN if rescan else 0)
     cfg.lane_max_degree = lane_max_degree
     return lpa_workspace_bytes(n, nnz, k, max_iter, cfg)
 
@@ -406,10 +409,10 @@ class Batch:
     iteration (see lpa_batch_create in include/lpa.h)."""
 
     def __init__(self, capacity: int, k: int = 8, mode: str = "det", check_every: int = 0,
-                 stream=None, device=None, rule: str = "mg"):
+                 stream=None, device=None, rule: str = "mg", rescan: bool = False):
         import torch
         cfg = lpa_config_default()
-        cfg.flags = MODES[mode] | RULES[rule]
+        cfg.flags = MODES[mode] | RULES[rule] | (LPA_RESCAN if rescan else 0)
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream

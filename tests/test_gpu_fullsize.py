@@ -124,3 +124,17 @@ def test_rmat22_bm_paper_det_exact():
     assert np.array_equal(dn, rdn) and np.array_equal(sc, rsc)
     assert np.array_equal(s.labels(device=False), ref)
     s.close()
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_rescan_det_exact():
+    # the double scan at full size, whole det run against the oracle
+    g = graph(22, False)
+    s = solver(g, k=8, mode="det", rescan=True)
+    it = s.run()
+    ref, rit, rdn, rsc = oracle.lpa_run(g.row_ptr, g.col, None, k=8, rescan=True)
+    assert it == rit
+    dn, sc = s.trace()
+    assert np.array_equal(dn, rdn) and np.array_equal(sc, rsc)
+    assert np.array_equal(s.labels(device=False), ref)
+    s.close()

@@ -32,10 +32,11 @@ def to_dev(g):
     return rp, col, w
 
 
-def gpu_run(g, k, mode="det", tol=0.05, max_iter=20, rho=8, lane_max_degree=0, rule="mg"):
+def gpu_run(g, k, mode="det", tol=0.05, max_iter=20, rho=8, lane_max_degree=0, rule="mg",
+            rescan=False):
     rp, col, w = to_dev(g)
     s = lpa.LPA(rp, col, w, k=k, tol=tol, max_iter=max_iter, rho=rho, mode=mode,
-                lane_max_degree=lane_max_degree, rule=rule)
+                lane_max_degree=lane_max_degree, rule=rule, rescan=rescan)
     it = s.run()
     labels = s.labels(device=False)
     dn, sc = s.trace()
@@ -120,7 +121,8 @@ def check_det(g, k, **kw):
     tol = kw.get("tol", 0.05)
     ok = oracle.BM_PAPER if kw.get("rule") == "bm_paper" else k
     ref, rit, rdn, rsc = oracle.lpa_run(g.row_ptr, g.col, g.w, k=ok, tol=tol,
-                                        max_iter=kw.get("max_iter", 20), rho=kw.get("rho", 8))
+                                        max_iter=kw.get("max_iter", 20), rho=kw.get("rho", 8),
+                                        rescan=kw.get("rescan", False))
     assert it == rit, (g.name, k, it, rit)
     assert np.array_equal(dn, rdn), (g.name, k, dn, rdn)
     assert np.array_equal(sc, rsc), (g.name, k, sc, rsc)
@@ -346,4 +348,56 @@ def test_bm_paper_batch():
     with pytest.raises(lpa.LpaError):
         mg_batch.run([solvers[0]])
     for x in solvers + [mg, batch, mg_batch]:
+        x.close()
+
+
+# ---- the double scan (LPA_RESCAN, Section 4.4 / Algorithm 4) --------------
+
+@pytest.mark.parametrize("name", GRAPHS)
+@pytest.mark.parametrize("k", [1, 2, 8])
+def test_rescan_det_parity(name, k):
+    check_det(graph(name), k, rescan=True)
+
+
+@pytest.mark.parametrize("lane_max", [1, 64])
+def test_rescan_det_independent_of_bins(lane_max):
+    # lane_max 1 sends every vertex of degree > 1 through the wavefront path
+    check_det(graph("rmat14-w"), 8, rescan=True, lane_max_degree=lane_max)
+
+
+@pytest.mark.parametrize("lane_max", [0, 64])
+def test_rescan_async_quality_and_validity(lane_max):
+    # lane_max 64 splits every vertex above 64 into hub segments, so the
+    # segment re-weighting and hub decision kernels run on many hubs
+    for name in ("sbm1-s1", "rmat14-w"):
+        g = graph(name)
+        labels, it, dn, sc, q = gpu_run(g, 8, "async", rescan=True, lane_max_degree=lane_max)
+        assert 1 <= it <= 20
+        assert labels.min() >= 0 and labels.max() < g.n
+        assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, labels)) <= 1e-9
+        if name == "sbm1-s1":
+            q_exact = oracle.modularity(g.row_ptr, g.col, None,
+                                        oracle.lpa_run(g.row_ptr, g.col, None, k=0)[0])
+            assert q > 0.9 * q_exact, (q, q_exact)
+
+
+def test_rescan_batch_and_rejections():
+    gs = [graph("sbm1-s1"), graph("rmat12"), graph("star5000")]
+    solvers = []
+    for g in gs:
+        rp, col, w = to_dev(g)
+        solvers.append(lpa.LPA(rp, col, w, k=4, rescan=True))
+    batch = lpa.Batch(len(gs), k=4, rescan=True)
+    batch.run(solvers)
+    for g, s in zip(gs, solvers):
+        ref = oracle.lpa_run(g.row_ptr, g.col, g.w, k=4, rescan=True)[0]
+        assert np.array_equal(s.labels(device=False), ref), g.name
+    rp, col, w = to_dev(gs[0])
+    single = lpa.LPA(rp, col, w, k=4)
+    with pytest.raises(lpa.LpaError):
+        batch.run([single])
+    with pytest.raises(lpa.LpaError) as ei:
+        lpa.LPA(rp, col, w, k=1, rule="bm_paper", rescan=True)
+    assert ei.value.code == lpa.LPA_ERR_ARG
+    for x in solvers + [single, batch]:
         x.close()
