@@ -317,6 +317,9 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--weights", default="uniform", choices=["uniform", "unit"])
     ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--host-csr", action="store_true",
+                    help="keep row_ptr / col / weights in pinned host memory (the kernels read "
+                         "them over the host link; only the O(|V|) state is in device memory)")
     ap.add_argument("--rescan", action="store_true",
                     help="double scan: re-weight the sketch's labels exactly in a second pass")
     ap.add_argument("--rule", default="mg", choices=["mg", "bm_paper"],
@@ -383,9 +386,14 @@ def main():
     workload = f"{gname}-{args.mode}-{rule_tag}"
 
     t = time.perf_counter()
-    rp = torch.from_numpy(g.row_ptr).to(dev)
-    col = torch.from_numpy(g.col).to(dev)
-    w = torch.from_numpy(g.w).to(dev) if g.w is not None else None
+    if args.host_csr:
+        place = lambda a: torch.from_numpy(a).pin_memory()  # noqa: E731
+        workload += "-hostcsr"
+    else:
+        place = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    rp = place(g.row_ptr)
+    col = place(g.col)
+    w = place(g.w) if g.w is not None else None
     torch.cuda.synchronize()
     h2d_s = time.perf_counter() - t
     stream = torch.cuda.current_stream(dev)

@@ -133,7 +133,26 @@ typedef struct lpa_batch lpa_batch;
 /* Fill *cfg with the defaults (det mode, rho 8, null stream, validation on). */
 void lpa_config_default(lpa_config *cfg);
 
-/* Create a handle for graph g.
+/* Where the library's kernels would read an array from (values of
+ * *location): LPA_PTR_DEVICE device or managed memory of the current device;
+ * LPA_PTR_HOST pinned host memory mapped into the device's address space
+ * (hipHostMalloc), read over the host link at the same address;
+ * LPA_PTR_UNUSABLE anything else (pageable host memory, another device's
+ * memory, NULL).  The graph arrays of lpa_init and the labels of
+ * lpa_modularity may be device or mapped host memory; anything else is
+ * refused with LPA_ERR_ARG before a kernel could touch it.  A CSR kept in
+ * pinned host memory leaves only the O(|V|) state of the method in device
+ * memory (Section 6 names keeping the input graph outside device memory as
+ * the way to larger graphs); every iteration then streams it over the
+ * link.
+ * Synchronises nothing; no device work. */
+#define LPA_PTR_UNUSABLE 0
+#define LPA_PTR_DEVICE 1
+#define LPA_PTR_HOST 2
+int lpa_pointer_location(const void *ptr, int *location);
+
+/* Create a handle for graph g (its arrays: device or mapped pinned host
+ * memory, see lpa_pointer_location; LPA_ERR_ARG otherwise).
  *   weights  device fp32[nnz] edge weights, symmetric, finite, > 0;
  *            NULL = every weight 1.0 (borrowed like the graph)
  *   k        sketch slots: 1 (weighted Boyer-Moore), 2, 4, 8, 16 or 32
@@ -199,8 +218,8 @@ int lpa_batch_free(lpa_batch *b);
 int lpa_progress(const lpa_handle *h, int *iteration, int *finished);
 
 /* Modularity Q of Eq. 1, community-sum form, accumulated in fp64.
- * labels: device int32[n] with values in [0, n), or NULL for the handle's
- * current labels.  Returns LPA_ERR_GRAPH (and leaves *q unset) if a label
+ * labels: device (or mapped pinned host) int32[n] with values in [0, n),
+ * or NULL for the handle's current labels; LPA_ERR_ARG for other memory.  Returns LPA_ERR_GRAPH (and leaves *q unset) if a label
  * is out of range.  Synchronises. */
 int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q);
 

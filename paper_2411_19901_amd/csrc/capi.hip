@@ -349,6 +349,37 @@ int fail_hip_b(lpa_batch *b, hipError_t e, const char *what) {
 
 bool k_supported(int k) { return k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32; }
 
+// Where an array handed to the library lives, as the kernels will see it:
+// device (or managed) memory of the current device, pinned host memory
+// mapped into the device's address space (read over the host link at the
+// same virtual address), or neither.  Classified before any kernel touches
+// the array.
+int pointer_location(const void *p) {
+  if (!p) return LPA_PTR_UNUSABLE;
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return LPA_PTR_UNUSABLE;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return LPA_PTR_UNUSABLE;
+  }
+  switch (at.type) {
+    case hipMemoryTypeDevice:
+    case hipMemoryTypeUnified:
+      return at.device == dev ? LPA_PTR_DEVICE : LPA_PTR_UNUSABLE;
+    case hipMemoryTypeManaged:
+      return LPA_PTR_DEVICE;
+    case hipMemoryTypeHost:
+      return (at.devicePointer == p) ? LPA_PTR_HOST : LPA_PTR_UNUSABLE;
+    default:
+      return LPA_PTR_UNUSABLE;
+  }
+}
+
 // Check k against the rule flags: LPA_ERR_UNSUPPORTED for a k without
 // kernels, LPA_ERR_ARG for the one-candidate vote with k != 1.
 int check_k(int k, uint32_t flags) {
@@ -648,6 +679,12 @@ const char *lpa_error_string(int code) {
 
 const char *lpa_last_error(const lpa_handle *h) { return h ? h->err.c_str() : ""; }
 
+int lpa_pointer_location(const void *ptr, int *location) {
+  if (!location) return LPA_ERR_ARG;
+  *location = pointer_location(ptr);
+  return LPA_OK;
+}
+
 static int check_config(const lpa_config &cfg) {
   for (int i = 0; i < 4; ++i)
     if (cfg.reserved[i] != 0) return LPA_ERR_ARG;
@@ -710,6 +747,10 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   if (g->n == 0 && g->nnz != 0) return LPA_ERR_ARG;
   if (!(tol >= 0.0 && tol <= 1.0) || max_iter < 0) return LPA_ERR_ARG;
   if ((rc = check_k(k, cfg.flags)) != LPA_OK) return rc;
+  // graph arrays the kernels could not read are refused here, not faulted on
+  if (g->n > 0 && pointer_location(g->row_ptr) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
+  if (g->nnz > 0 && pointer_location(g->col_idx) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
+  if (weights && g->nnz > 0 && pointer_location(weights) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
 
   lpa_handle *h = new (std::nothrow) lpa_handle();
   if (!h) return LPA_ERR_NOMEM;
@@ -1025,6 +1066,8 @@ int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q) {
     h->mod_acc = (double *)((char *)p + align_up((size_t)n * sizeof(double)));
     hipLaunchKernelGGL(k_zero_d, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->mod_tot, n);
   }
+  if (labels && pointer_location(labels) == LPA_PTR_UNUSABLE)
+    return set_err(h, LPA_ERR_ARG, "labels must be device or mapped pinned host memory");
   const int32_t *lab = labels ? labels : cur_labels(h);
   const GraphDesc &d = h->desc;
   hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);

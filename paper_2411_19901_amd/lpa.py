@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
         "lpa_batch_free": (ctypes.c_int, [H]),
         "lpa_error_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lpa_last_error": (ctypes.c_char_p, [H]),
+        "lpa_pointer_location": (ctypes.c_int, [ctypes.c_void_p, ip]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -118,6 +119,17 @@ def header_functions(header: str = HEADER):
     """Names of the functions declared in include/lpa.h."""
     text = open(header).read()
     return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lpa_\w+)\s*\(", text, re.M)))
+
+
+LPA_PTR_UNUSABLE, LPA_PTR_DEVICE, LPA_PTR_HOST = 0, 1, 2
+
+
+def pointer_location(ptr: int) -> int:
+    """Where the kernels would read an array at address ``ptr`` from."""
+    loc = ctypes.c_int(-1)
+    _check(load().lpa_pointer_location(ctypes.c_void_p(ptr), ctypes.byref(loc)),
+           "lpa_pointer_location")
+    return loc.value
 
 
 def error_string(code: int) -> str:
@@ -295,17 +307,22 @@ class LPA:
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
                  stream=None, workspace=None, rule: str = "mg", rescan: bool = False):
         import torch
+
+        def usable(t):  # device memory, or pinned host memory the device maps
+            return t.is_cuda or (t.device.type == "cpu" and t.is_pinned())
+
         for t, dt in ((row_ptr, torch.int32), (col, torch.int32)):
-            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
-                raise ValueError("row_ptr / col must be contiguous int32 CUDA tensors")
-        if weights is not None and (weights.dtype != torch.float32 or not weights.is_cuda
+            if t.dtype != dt or not usable(t) or not t.is_contiguous():
+                raise ValueError("row_ptr / col must be contiguous int32 CUDA (or pinned) tensors")
+        if weights is not None and (weights.dtype != torch.float32 or not usable(weights)
                                     or not weights.is_contiguous()):
-            raise ValueError("weights must be a contiguous float32 CUDA tensor")
+            raise ValueError("weights must be a contiguous float32 CUDA (or pinned) tensor")
         self._keep = (row_ptr, col, weights)
         self.n = row_ptr.numel() - 1
         self.nnz = col.numel()
         self.max_iter = max_iter
-        self.device = row_ptr.device
+        self.device = (row_ptr.device if row_ptr.is_cuda
+                       else torch.device("cuda", torch.cuda.current_device()))
         cfg = lpa_config_default()
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
                      | (LPA_RESCAN if rescan else 0))
