@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -72,64 +73,122 @@ __global__ void k_check_labels(const int32_t *lab, int n, int *bad) {
 }
 
 // --- degree binning: histogram -> exclusive scan -> scatter ---------------
-__global__ void k_bin_hist(int n, const int32_t *rp, int lane_max, int ncls, unsigned *hist) {
-  extern __shared__ unsigned sh[];
-  for (int c = threadIdx.x; c < ncls; c += blockDim.x) sh[c] = 0;
+// Stable degree binning (once per graph): vertices ordered by degree class
+// (decreasing degree), increasing id within a class; isolated vertices are
+// left out.  Block b owns the ids [b * kBinIds, (b + 1) * kBinIds).
+//   1. k_bin_count: counts[c * nblk + b] = vertices of class c in block b;
+//   2. k_scan_*: exclusive prefix sum over counts in (class, block) order,
+//      which is each block's first position for each class;
+//   3. k_bin_place: every block walks its ids in order and writes each
+//      vertex at its class's next position.
+constexpr int kBinIds = 4096;
+constexpr int kScanChunk = 4096;  // entries per block of the prefix sum
+
+__global__ void k_bin_count(int n, const int32_t *rp, int lane_max, int nblk, unsigned *counts) {
+  __shared__ unsigned cnt[kClasses];
+  for (int c = threadIdx.x; c < kClasses; c += blockDim.x) cnt[c] = 0;
   __syncthreads();
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  const int v0 = blockIdx.x * kBinIds;
+  for (int v = v0 + threadIdx.x; v < v0 + kBinIds && v < n; v += blockDim.x) {
     const int d = rp[v + 1] - rp[v];
-    if (d > 0) atomicAdd(&sh[degree_class(d, lane_max)], 1u);
+    if (d > 0) atomicAdd(&cnt[degree_class(d, lane_max)], 1u);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < ncls; c += blockDim.x)
-    if (sh[c]) atomicAdd(&hist[c], sh[c]);
+  for (int c = threadIdx.x; c < kClasses; c += blockDim.x)
+    counts[(size_t)c * nblk + blockIdx.x] = cnt[c];
 }
 
-// hist becomes exclusive offsets; totals[0] = hubs, totals[1] = lane vertices
-__global__ void k_bin_scan(int ncls, unsigned *hist, int *totals) {
-  if (threadIdx.x != 0) return;
-  unsigned acc = 0, hubs = 0;
-  for (int c = 0; c < ncls; ++c) {
-    const unsigned x = hist[c];
-    hist[c] = acc;
-    acc += x;
-    if (c < kHubClasses) hubs += x;
+// In-place exclusive scan of each kScanChunk-entry chunk; chunk totals to
+// sums[chunk].  256 threads, 16 consecutive entries per thread.
+__global__ void k_scan_chunks(unsigned *x, size_t count, unsigned *sums) {
+  __shared__ unsigned part[256];
+  const size_t base = (size_t)blockIdx.x * kScanChunk + (size_t)threadIdx.x * 16;
+  unsigned loc[16];
+  unsigned t = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    loc[i] = base + i < count ? x[base + i] : 0u;
+    t += loc[i];
   }
+  part[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the 256 thread totals
+    const unsigned y = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  unsigned run = part[threadIdx.x] - t;  // exclusive
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (base + i < count) x[base + i] = run;
+    run += loc[i];
+  }
+  if (threadIdx.x == 255) sums[blockIdx.x] = part[255];
+}
+
+// Exclusive scan of the chunk totals (one block, sequential in the first
+// thread: there are at most a few hundred thousand chunks and it runs once
+// per graph); writes the number of hubs and of lane vertices.
+__global__ void k_scan_sums(unsigned *sums, int nchunks, const unsigned *x, int nblk,
+                            int *totals) {
+  if (threadIdx.x != 0) return;
+  unsigned acc = 0;
+  for (int c = 0; c < nchunks; ++c) {
+    const unsigned y = sums[c];
+    sums[c] = acc;
+    acc += y;
+  }
+  // first position of class kHubClasses (block 0) = number of hubs
+  const size_t i = (size_t)kHubClasses * nblk;
+  const unsigned hubs = x[i] + sums[i / kScanChunk];
   totals[0] = (int)hubs;
   totals[1] = (int)(acc - hubs);
 }
 
-constexpr int kScatterItems = 16;
-__global__ void k_bin_scatter(int n, const int32_t *rp, int lane_max, int ncls, unsigned *cursor,
-                              int32_t *order) {
-  extern __shared__ unsigned sh[];  // [ncls] local counts, then [ncls] bases
-  unsigned *cnt = sh;
-  unsigned *base = sh + ncls;
-  for (int c = threadIdx.x; c < ncls; c += blockDim.x) cnt[c] = 0;
+__global__ void k_scan_add(unsigned *x, size_t count, const unsigned *sums) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) x[i] += sums[i / kScanChunk];
+}
+
+// Place every vertex of block b at its class's next position, in id order.
+// 256 threads walk the block's ids 256 at a time; the four wavefronts take
+// turns so that lower ids are placed first.
+__global__ __launch_bounds__(256) void k_bin_place(int n, const int32_t *rp, int lane_max, int nblk,
+                                                   const unsigned *offsets, int32_t *order) {
+  __shared__ unsigned next[kClasses];
+  for (int c = threadIdx.x; c < kClasses; c += blockDim.x) next[c] = 0;
   __syncthreads();
-  const int v0 = blockIdx.x * blockDim.x * kScatterItems;
-  int cls[kScatterItems];
-  unsigned rank[kScatterItems];
-#pragma unroll
-  for (int t = 0; t < kScatterItems; ++t) {
-    const int v = v0 + t * blockDim.x + threadIdx.x;
-    cls[t] = -1;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int v0 = blockIdx.x * kBinIds;
+  for (int r = 0; r < kBinIds; r += 256) {
+    const int v = v0 + r + (int)threadIdx.x;
+    int cls = -1;
     if (v < n) {
       const int d = rp[v + 1] - rp[v];
-      if (d > 0) {
-        cls[t] = degree_class(d, lane_max);
-        rank[t] = atomicAdd(&cnt[cls[t]], 1u);
-      }
+      if (d > 0) cls = degree_class(d, lane_max);
     }
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < ncls; c += blockDim.x)
-    base[c] = cnt[c] ? atomicAdd(&cursor[c], cnt[c]) : 0u;
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < kScatterItems; ++t) {
-    const int v = v0 + t * blockDim.x + threadIdx.x;
-    if (cls[t] >= 0) order[base[cls[t]] + rank[t]] = v;
+    for (int w = 0; w < 4; ++w) {
+      if (wid == w) {
+        unsigned long long rest = __ballot(cls >= 0);
+        while (rest) {
+          const int src = __ffsll((long long)rest) - 1;
+          const int c = __shfl(cls, src);
+          const unsigned long long m = __ballot(cls == c);
+          rest &= ~m;
+          const unsigned start = next[c];
+          if (cls == c) {
+            const unsigned rank = (unsigned)__popcll(m & below);
+            order[offsets[(size_t)c * nblk + blockIdx.x] + start + rank] = v;
+          }
+          if (lane == src) next[c] = start + (unsigned)__popcll(m);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -423,16 +482,20 @@ Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode,
     return at;
   };
   const size_t T = (size_t)(max_iter > 0 ? max_iter : 1);
-  L.ncls = kHubClasses + lane_max + 1;
+  L.ncls = kClasses;
+  const size_t nblk = ((size_t)n + kBinIds - 1) / kBinIds;
+  const size_t cells = (size_t)kClasses * (nblk ? nblk : 1);
+  const size_t chunks = (cells + kScanChunk - 1) / kScanChunk;
   L.st = take(sizeof(GraphStatus));
   L.dN = take(T * 8);
   L.scanned = take(T * 8);
-  L.C0 = take((size_t)n * 4);
+  // the binning's count matrix uses C0 before the labels are initialised
+  L.C0 = take(std::max((size_t)n * 4, cells * 4));
   L.C1 = async_mode ? L.C0 : take((size_t)n * 4);
   L.act0 = take((size_t)n);
   L.act1 = async_mode ? L.act0 : take((size_t)n);
   L.order = take((size_t)n * 4);
-  L.hist = take((size_t)L.ncls * 4);
+  L.hist = take(chunks * 4);
   if (async_mode) {
     // hubs have more than S entries each; a hub of degree d > S has
     // ceil(d / S) < 2 d / S segments
@@ -838,18 +901,20 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
 
   // degree binning (once per graph)
   if (n > 0) {
-    const int ncls = Ly.ncls;
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(ncls)), dim3(kAuxBlock), 0, h->stream,
-                       (int32_t *)h->hist, ncls);
-    hipLaunchKernelGGL(k_bin_hist, dim3(grid_for(n, kAuxBlock, 2048)), dim3(kAuxBlock),
-                       ncls * sizeof(unsigned), h->stream, n, h->row_ptr, h->lane_max, ncls,
+    const int nblk = (n + kBinIds - 1) / kBinIds;
+    const size_t cells = (size_t)kClasses * nblk;
+    const int nchunks = (int)((cells + kScanChunk - 1) / kScanChunk);
+    unsigned *counts = (unsigned *)d.C[0];
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, h->stream, n, h->row_ptr,
+                       h->lane_max, nblk, counts);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunks), dim3(256), 0, h->stream, counts, cells,
                        (unsigned *)h->hist);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(64), 0, h->stream, ncls, (unsigned *)h->hist,
-                       h->st->totals);
-    const int per_block = kAuxBlock * kScatterItems;
-    hipLaunchKernelGGL(k_bin_scatter, dim3((n + per_block - 1) / per_block), dim3(kAuxBlock),
-                       2 * ncls * sizeof(unsigned), h->stream, n, h->row_ptr, h->lane_max, ncls,
-                       (unsigned *)h->hist, (int32_t *)d.order);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, h->stream, (unsigned *)h->hist, nchunks,
+                       counts, nblk, h->st->totals);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, h->stream,
+                       counts, cells, (const unsigned *)h->hist);
+    hipLaunchKernelGGL(k_bin_place, dim3(nblk), dim3(256), 0, h->stream, n, h->row_ptr,
+                       h->lane_max, nblk, (const unsigned *)counts, (int32_t *)d.order);
     int totals[4] = {0, 0, 0, 0};
     if (hipGetLastError() != hipSuccess ||
         hipMemcpyAsync(totals, h->st->totals, sizeof(totals), hipMemcpyDeviceToHost, h->stream) !=

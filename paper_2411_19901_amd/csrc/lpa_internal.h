@@ -13,16 +13,25 @@ constexpr int kBlock = 256;  // threads per workgroup for the move kernels
 
 // Degree classes used to order vertices by decreasing degree.  Classes
 // 0..255 hold hubs (degree > lane_max) on a log scale with eight
-// sub-buckets per octave; classes 256..256+T-1 hold degrees T..1 exactly.
+// sub-buckets per octave; lane degrees 65..lane_max (lane_max <= 65536)
+// use the same eighth-of-an-octave buckets (classes 256..343); degrees
+// 64..1 have one class each (344..407).  Within a class vertices keep
+// increasing id order (the binning is stable).
 constexpr int kHubClasses = 256;
+constexpr int kLaneBuckets = 88;  // eighth-octave buckets for degrees 65 .. 2^17 - 1
+constexpr int kLaneExact = 64;    // one class per degree 1 .. 64
+constexpr int kClasses = kHubClasses + kLaneBuckets + kLaneExact;
+
+__host__ __device__ inline int octave_bucket(int d) {  // d >= 1
+  const int b = 31 - __builtin_clz((unsigned)d);
+  const int sub = b >= 3 ? (d >> (b - 3)) & 7 : (d << (3 - b)) & 7;
+  return b * 8 + sub;
+}
 
 __host__ __device__ inline int degree_class(int d, int lane_max) {
-  if (d > lane_max) {
-    int b = 31 - __builtin_clz((unsigned)d);
-    int sub = b >= 3 ? (d >> (b - 3)) & 7 : (d << (3 - b)) & 7;
-    return kHubClasses - 1 - (b * 8 + sub);
-  }
-  return kHubClasses + (lane_max - d);
+  if (d > lane_max) return kHubClasses - 1 - octave_bucket(d);
+  if (d > kLaneExact) return kHubClasses + kLaneBuckets - 1 - (octave_bucket(d) - 6 * 8);
+  return kHubClasses + kLaneBuckets + (kLaneExact - d);
 }
 
 // Device-resident progress of one graph, updated by the convergence kernel.

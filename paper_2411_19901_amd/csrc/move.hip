@@ -650,17 +650,11 @@ __global__ void k_hub_snapshot(Launch L) {
   }
 }
 
-// A moved hub marks its neighbours, row-contiguous, one hub at a time
-// (all lanes call it together; `moved` and `v` are per lane).
-__device__ __forceinline__ void mark_moved_hubs(const MoveArgs &a, bool moved, int v, int lane) {
-  unsigned long long rest = __ballot(moved);
-  while (rest) {
-    const int src = __ffsll((long long)rest) - 1;
-    rest &= rest - 1;
-    const int bv = __shfl(v, src);
-    const int rb = a.row_ptr[bv], re = a.row_ptr[bv + 1];
-    for (int e = rb + lane; e < re; e += kWave) mark(a, __builtin_nontemporal_load(a.col + e));
-  }
+// A hub's decision is recorded in hub_act (its flag snapshot is no longer
+// needed once the hub is decided): 1 if its label moved.  k_hub_mark then
+// flags the neighbours of moved hubs, one wavefront per hub segment.
+__device__ __forceinline__ void record_moved_hub(const MoveArgs &a, int h, bool moved) {
+  if (h < a.n_hubs) a.hub_act[h] = moved ? 1 : 0;
 }
 
 // Merge the partial sketches of every active hub (Section 4.3).  A wavefront
@@ -767,7 +761,7 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
       const bool moved = active && c != cv && (!a.pickless || c < cv);
       if (moved) a.C[v] = c;
       changed_w += (unsigned long long)__popcll(__ballot(moved));
-      mark_moved_hubs(a, moved, v, lane);
+      record_moved_hub(a, h, moved);
     }
   }
   flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
@@ -913,9 +907,31 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
     const bool moved = active && c != cv && (!a.pickless || c < cv);
     if (moved) a.C[v] = c;
     changed_w += (unsigned long long)__popcll(__ballot(moved));
-    mark_moved_hubs(a, moved, v, lane);
+    record_moved_hub(a, h, moved);
   }
   flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
+}
+
+// Flag the neighbours of every hub that moved in this iteration: one
+// wavefront per hub segment, coalesced column loads.
+__global__ __launch_bounds__(kBlock) void k_hub_mark(Launch L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = rfl((blockIdx.x * kBlock + threadIdx.x) / kWave);
+  const int nwaves = gridDim.x * (kBlock / kWave);
+  for (int item = wave; item < L.total_segs; item += nwaves) {
+    const int g = rfl(find_graph(L.prefix_segs, L.G, item));
+    const GraphDesc &gd = L.d[g];
+    if (gd.st->done) continue;
+    const MoveArgs a = make_args(gd, gd.st->iter);
+    const int u = item - L.prefix_segs[g];
+    const int h = a.seg_hub[u];
+    if (a.hub_act[h] == 0) continue;
+    const int v = a.order[h];
+    const int q = u - a.hub_pbase[h];
+    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
+    const int beg = rb + q * a.seg_len, end = min(beg + a.seg_len, re);
+    for (int e = beg + lane; e < end; e += kWave) mark(a, __builtin_nontemporal_load(a.col + e));
+  }
 }
 
 // Convergence test of Algorithm 1 for every graph of the launch: after
@@ -967,6 +983,7 @@ static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_
     } else {
       hipLaunchKernelGGL((k_hub_merge<K>), dim3(merge_grid), dim3(kBlock), 0, s, L);
     }
+    if (L.total_segs > 0) hipLaunchKernelGGL(k_hub_mark, dim3(grid), dim3(kBlock), 0, s, L);
   }
   const int fg = (L.G + 255) / 256 < 64 ? (L.G + 255) / 256 : 64;
   hipLaunchKernelGGL(k_finish, dim3(fg > 0 ? fg : 1), dim3(256), 0, s, L);
