@@ -33,6 +33,35 @@ __device__ void add_by_label(double *tot, int c, double x, bool on) {
   }
 }
 
+// One step of TW entries per row (TW <= T), as in the move kernel's
+// staging: adds matching weights to `in` and stages the weights for the
+// row owners' K_i sums.
+template <int TW, int T>
+__device__ __forceinline__ void mod_step(const ModArgs &m, Stage<T> &st, int lane, int t0, int tn,
+                                         double &ki, double &in) {
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+    const int slot = i * kWave + lane;
+    const int r = slot / TW, j = slot % TW;
+    const int p = t0 + j;
+    float x = 0.0f;
+    if (p < st.len[r]) {
+      const int e = st.beg[r] + p;
+      const int c = __builtin_nontemporal_load(m.col + e);
+      x = m.w ? __builtin_nontemporal_load(m.w + e) : 1.0f;
+      if (m.lab[c] == st.self[r]) in += (double)x;
+    }
+    st.w[r * (TW + 1) + j] = x;
+  }
+  wave_lds_sync();
+  if (m.w) {
+#pragma unroll
+    for (int j = 0; j < TW; ++j)
+      if (j < tn) ki += (double)st.w[lane * (TW + 1) + j];
+  }
+  wave_lds_sync();
+}
+
 // One lane per row: entries [beg, beg + len) of vertex v (v < 0: none).
 template <int T>
 __device__ void mod_lane_rows(const ModArgs &m, Stage<T> &st, int lane, int v, double &k_acc,
@@ -49,27 +78,18 @@ __device__ void mod_lane_rows(const ModArgs &m, Stage<T> &st, int lane, int v, d
   const int maxlen = rfl(wave_max(len));
   wave_lds_sync();
   double ki = 0.0, in = 0.0;
-  for (int t0 = 0; t0 < maxlen; t0 += T) {
-#pragma unroll
-    for (int i = 0; i < T; ++i) {
-      const int slot = i * kWave + lane;
-      const int r = slot / T, j = slot % T;
-      const int p = t0 + j;
-      float x = 0.0f;
-      if (p < st.len[r]) {
-        const int e = st.beg[r] + p;
-        const int c = __builtin_nontemporal_load(m.col + e);
-        x = m.w ? __builtin_nontemporal_load(m.w + e) : 1.0f;
-        if (m.lab[c] == st.self[r]) in += (double)x;
-      }
-      st.w[r * (T + 1) + j] = x;
+  for (int t0 = 0; t0 < maxlen;) {
+    const int rem = maxlen - t0;
+    if (rem <= 4) {
+      mod_step<4>(m, st, lane, t0, rem, ki, in);
+      t0 += 4;
+    } else if (rem <= 8) {
+      mod_step<8>(m, st, lane, t0, rem, ki, in);
+      t0 += 8;
+    } else {
+      mod_step<T>(m, st, lane, t0, min(T, rem), ki, in);
+      t0 += T;
     }
-    wave_lds_sync();
-    if (m.w) {
-#pragma unroll
-      for (int j = 0; j < T; ++j) ki += (double)st.w[lane * (T + 1) + j];
-    }
-    wave_lds_sync();
   }
   if (!m.w) ki = (double)len;
   k_acc += ki;

@@ -156,6 +156,36 @@ constexpr int slots_of(int K) { return K == 0 ? 1 : K; }
 
 // Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
 // nothing).  All lanes of the wavefront must call it together.
+// Load one staging step of TW entries for each of the 64 rows (TW <= T):
+// slot i * 64 + lane holds entry t0 + j of row r, (r, j) = (slot / TW,
+// slot % TW), stored at r * (TW + 1) + j.
+template <int TW, int T>
+__device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T> &st, int lane, int t0) {
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+    const int slot = i * kWave + lane;
+    const int r = slot / TW, j = slot % TW;
+    const int p = t0 + j;
+    int lab = -1;
+    float x = 0.0f;
+    if (p < st.len[r]) {
+      const int e = st.beg[r] + p;
+      const int c = __builtin_nontemporal_load(a.col + e);
+      x = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
+      if (c == st.self[r]) x = 0.0f;
+      lab = a.C[c];
+    }
+    st.lab[r * (TW + 1) + j] = lab;
+    st.w[r * (TW + 1) + j] = x;
+  }
+}
+
+// Feed entries [beg, beg + len) of row `self` to feed(label, weight) in CSR
+// order (len = 0: nothing); entries of the vertex itself come with weight 0.
+// All lanes of the wavefront must call it together.  Each step takes 4, 8
+// or T entries per row, the narrowest that covers what the wavefront's
+// longest row has left: with short rows a wide step would leave most load
+// slots idle.
 template <int T, class Feed>
 __device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T> &st, int lane, int beg,
                                             int len, int self, Feed &&feed) {
@@ -164,32 +194,23 @@ __device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T> &st, int
   st.self[lane] = self;
   const int maxlen = rfl(wave_max(len));
   wave_lds_sync();
-  for (int t0 = 0; t0 < maxlen; t0 += T) {
-#pragma unroll
-    for (int i = 0; i < T; ++i) {
-      const int slot = i * kWave + lane;
-      const int r = slot / T, j = slot % T;
-      const int p = t0 + j;
-      int lab = -1;
-      float x = 0.0f;
-      if (p < st.len[r]) {
-        const int e = st.beg[r] + p;
-        const int c = __builtin_nontemporal_load(a.col + e);
-        x = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
-        if (c == st.self[r]) x = 0.0f;
-        lab = a.C[c];
-      }
-      st.lab[r * (T + 1) + j] = lab;
-      st.w[r * (T + 1) + j] = x;
-    }
+  for (int t0 = 0; t0 < maxlen;) {
+    const int rem = maxlen - t0;
+    const int tw = rem <= 4 ? 4 : (rem <= 8 ? 8 : T);
+    if (tw == 4)
+      stage_load<4>(a, st, lane, t0);
+    else if (tw == 8)
+      stage_load<8>(a, st, lane, t0);
+    else
+      stage_load<T>(a, st, lane, t0);
     wave_lds_sync();
-    // columns past the longest row of the wavefront hold only padding
-    // (label -1, weight 0), so the uniform bound tn skips them
-    const int tn = min(T, maxlen - t0);
-#pragma unroll
-    for (int j = 0; j < T; ++j)
-      if (j < tn) feed(st.lab[lane * (T + 1) + j], st.w[lane * (T + 1) + j]);
+    // this lane's row: its first tn staged entries (later columns of the
+    // step are padding for every row: label -1, weight 0)
+    const int tn = min(tw, rem);
+    const int row = lane * (tw + 1);
+    for (int j = 0; j < tn; ++j) feed(st.lab[row + j], st.w[row + j]);
     wave_lds_sync();
+    t0 += tw;
   }
 }
 
@@ -240,6 +261,20 @@ __device__ __forceinline__ void mark(const MoveArgs &a, int j) { a.act_next[j] =
 
 // Mark the neighbours of every lane whose `moved` is set (entries [beg, beg +
 // len) of its row), with row-contiguous column loads by the whole wavefront.
+template <int TW, int T>
+__device__ __forceinline__ void mark_step(const MoveArgs &a, const Stage<T> &st, int lane, int t0) {
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+    const int slot = i * kWave + lane;
+    const int r = slot / TW, j = slot % TW;
+    const int p = t0 + j;
+    if (p < st.len[r]) mark(a, __builtin_nontemporal_load(a.col + st.beg[r] + p));
+  }
+}
+
+// Mark the neighbours of every lane whose `moved` is set (entries [beg, beg +
+// len) of its row), with row-contiguous column loads by the whole wavefront
+// and the same step widths as staged_rows.
 template <int T>
 __device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T> &st, int lane, int beg,
                                             int len, bool moved) {
@@ -248,13 +283,17 @@ __device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T> &st, int
   st.len[lane] = moved ? len : 0;
   const int maxlen = rfl(wave_max(moved ? len : 0));
   wave_lds_sync();
-  for (int t0 = 0; t0 < maxlen; t0 += T) {
-#pragma unroll
-    for (int i = 0; i < T; ++i) {
-      const int slot = i * kWave + lane;
-      const int r = slot / T, j = slot % T;
-      const int p = t0 + j;
-      if (p < st.len[r]) mark(a, __builtin_nontemporal_load(a.col + st.beg[r] + p));
+  for (int t0 = 0; t0 < maxlen;) {
+    const int rem = maxlen - t0;
+    if (rem <= 4) {
+      mark_step<4>(a, st, lane, t0);
+      t0 += 4;
+    } else if (rem <= 8) {
+      mark_step<8>(a, st, lane, t0);
+      t0 += 8;
+    } else {
+      mark_step<T>(a, st, lane, t0);
+      t0 += T;
     }
   }
   wave_lds_sync();
