@@ -103,13 +103,22 @@ def cpu_baseline(g, k, seconds, rng_seed=0):
     edges1 = int(deg[one].sum())
     dt1 = timed(one, 1)
     what = f"k={k}" if k > 0 else "vote of Algorithm 3"
+    # the exact rule of Eq. 3 (dense per-thread accumulator), same sample size
+    ex = sized(rate, seconds / 4)
+    edges_x = int(deg[ex].sum())
+    tx = time.perf_counter()
+    oracle.lpa_choose(g.row_ptr, g.col, g.w, 0, True, C, ex)
+    dtx = max(time.perf_counter() - tx, 1e-6)
     return {"value": round(edges / dt / 1e9, 4), "unit": "GTEPS", "cores": int(nt),
             "kind": "oracle",
             "sample": f"{len(sample)} uniformly sampled non-isolated vertices ({edges} CSR entries, "
                       f"{100.0 * edges / g.nnz:.1f}% of the graph), one iteration-0 label choice each, "
                       f"{what}, {dt:.1f} s on {nt} threads",
             "single_core": {"value": round(edges1 / dt1 / 1e9, 4), "unit": "GTEPS", "cores": 1,
-                            "sample": f"{len(one)} vertices ({edges1} CSR entries), {dt1:.1f} s"}}
+                            "sample": f"{len(one)} vertices ({edges1} CSR entries), {dt1:.1f} s"},
+            "exact_rule": {"value": round(edges_x / dtx / 1e9, 4), "unit": "GTEPS", "cores": int(nt),
+                           "sample": f"{len(ex)} vertices ({edges_x} CSR entries), exact argmax "
+                                     f"of Eq. 3, {dtx:.1f} s"}}
 
 
 def build_graph(args):
@@ -131,6 +140,9 @@ def build_graph(args):
         name += "-wU(0,1]"
     else:
         name += "-w1"
+    if getattr(args, "permute", False):
+        g = inputs.permuted(g, 1000 + args.scale)
+        name += "-perm"
     log(f"[bench] generated {name}: n={g.n} nnz={g.nnz} in {time.perf_counter() - t:.1f}s")
     return g, name
 
@@ -317,9 +329,15 @@ def main():
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--weights", default="uniform", choices=["uniform", "unit"])
     ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--permute", action="store_true",
+                    help="relabel the vertices by a seeded random permutation (R-MAT ids carry "
+                         "locality; this is the locality-free copy)")
     ap.add_argument("--host-csr", action="store_true",
                     help="keep row_ptr / col / weights in pinned host memory (the kernels read "
                          "them over the host link; only the O(|V|) state is in device memory)")
+    ap.add_argument("--hub-shared", action="store_true",
+                    help="one shared LDS sketch per high-degree vertex instead of merged "
+                         "partial sketches (async ablation)")
     ap.add_argument("--rescan", action="store_true",
                     help="double scan: re-weight the sketch's labels exactly in a second pass")
     ap.add_argument("--rule", default="mg", choices=["mg", "bm_paper"],
@@ -382,7 +400,8 @@ def main():
     g, gname = build_graph(args)
     if args.rule == "bm_paper":
         args.k = 1
-    rule_tag = (f"k{args.k}" if args.rule == "mg" else "bm-paper") + ("-rescan" if args.rescan else "")
+    rule_tag = ((f"k{args.k}" if args.rule == "mg" else "bm-paper") + ("-rescan" if args.rescan else "")
+                + ("-hubshared" if args.hub_shared else ""))
     workload = f"{gname}-{args.mode}-{rule_tag}"
 
     t = time.perf_counter()
@@ -401,7 +420,7 @@ def main():
     t = time.perf_counter()
     solver = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
                      mode=args.mode, lane_max_degree=args.lane_max_degree, rule=args.rule,
-                     rescan=args.rescan,
+                     rescan=args.rescan, hub_shared=args.hub_shared,
                      check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t) * 1e3
@@ -498,6 +517,8 @@ def main():
         "init_ms": round(init_ms, 2),
         "h2d_s": round(h2d_s, 3),
         "bytes_per_vertex": round(core_bytes / g.n, 3),
+        # per-vertex hashtables of the earlier GPU method: 16 B per CSR entry
+        "hashtable_method_bytes_per_vertex": round(16 * g.nnz / g.n, 1),
         "hipmeminfo_bytes_per_vertex": round((free0 - free1) / g.n, 3),
         "gpu": torch.cuda.get_device_name(dev),
     }

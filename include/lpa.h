@@ -96,6 +96,15 @@ typedef enum lpa_status {
  * (LPA_ERR_ARG together with LPA_RULE_BM_PAPER).  Reads every processed row
  * twice. */
 #define LPA_RESCAN 0x400u
+/* Ablation of the partial sketches of Section 4.3 (LPA_MODE_ASYNC, sketch
+ * rule, no LPA_RESCAN; LPA_ERR_ARG otherwise): every vertex of degree above
+ * lane_max_degree is processed by one workgroup whose threads all update
+ * a single shared sketch in LDS with atomics, as in the shared mode of
+ * Algorithm 5 (add to a matching slot, claim a free slot by
+ * compare-and-swap with retries, otherwise decrement every slot), instead
+ * of per-segment sketches merged afterwards.  Updates race, so results are
+ * approximate and depend on scheduling. */
+#define LPA_HUB_SHARED 0x800u
 
 /* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji). */
 typedef struct lpa_graph {
@@ -107,7 +116,8 @@ typedef struct lpa_graph {
 
 typedef struct lpa_config {
   uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC,
-                              | LPA_VALIDATE, | LPA_RULE_BM_PAPER, | LPA_RESCAN */
+                              | LPA_VALIDATE, | LPA_RULE_BM_PAPER, | LPA_RESCAN,
+                              | LPA_HUB_SHARED */
   int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per

@@ -302,7 +302,8 @@ int grid_for(size_t count, int block = kAuxBlock, int cap = 4096) {
 struct lpa_batch {
   int capacity = 0;
   int k = 8;  // kernel selector: sketch slots, 0 = the vote of Algorithm 3
-  bool rescan = false;  // double scan (LPA_RESCAN)
+  bool rescan = false;      // double scan (LPA_RESCAN)
+  bool hub_shared = false;  // one shared sketch per hub (LPA_HUB_SHARED)
   bool async_mode = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -445,6 +446,9 @@ int check_k(int k, uint32_t flags) {
   if (!k_supported(k)) return LPA_ERR_UNSUPPORTED;
   if ((flags & LPA_RULE_BM_PAPER) && k != 1) return LPA_ERR_ARG;
   if ((flags & LPA_RULE_BM_PAPER) && (flags & LPA_RESCAN)) return LPA_ERR_ARG;
+  if ((flags & LPA_HUB_SHARED) &&
+      ((flags & LPA_MODE_MASK) != LPA_MODE_ASYNC || (flags & (LPA_RULE_BM_PAPER | LPA_RESCAN))))
+    return LPA_ERR_ARG;
   return LPA_OK;
 }
 
@@ -600,6 +604,7 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
     if (!h) return LPA_ERR_ARG;
     if (h->poisoned) return LPA_ERR_HIP;
     if (kernel_k(h->k, h->flags) != b->k || ((h->flags & LPA_RESCAN) != 0) != b->rescan ||
+        ((h->flags & LPA_HUB_SHARED) != 0) != b->hub_shared ||
         h->async_mode != b->async_mode || h->device != b->device || h->stream != b->stream)
       return LPA_ERR_ARG;
     for (int q = 0; q < g; ++q)
@@ -685,7 +690,8 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
       }
     }
     hipError_t e =
-        launch_iteration(b->k, b->async_mode, b->rescan, L, grid, mg, b->stream, eb, ee);
+        launch_iteration(b->k, b->async_mode, b->rescan, b->hub_shared, L, grid, mg, b->stream,
+                         eb, ee);
     if (e != hipSuccess) return fail_hip_b(b, e, "iteration launch");
     if (b->check_every > 0 && (i + 1) % b->check_every == 0 && i + 1 < iters) {
       HIP_TRY_B(b, hipMemcpyAsync(b->h_finished, b->d_finished, sizeof(int32_t),
@@ -756,7 +762,8 @@ static int check_config(const lpa_config &cfg) {
     return LPA_ERR_ARG;
   const uint32_t mode = cfg.flags & LPA_MODE_MASK;
   if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
-  if ((cfg.flags & ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN)) != 0)
+  if ((cfg.flags &
+       ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN | LPA_HUB_SHARED)) != 0)
     return LPA_ERR_UNSUPPORTED;
   if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
   return LPA_OK;
@@ -941,7 +948,8 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
                        d.hub_pbase, d.n_hubs, (int32_t *)d.seg_hub);
     if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
   }
-  d.items = h->async_mode ? (d.n_seg + d.n_lane + kWave - 1) / kWave
+  d.hub_shared = (cfg.flags & LPA_HUB_SHARED) ? 1 : 0;
+  d.items = h->async_mode ? ((d.hub_shared ? 0 : d.n_seg) + d.n_lane + kWave - 1) / kWave
                           : d.n_hubs + (d.n_lane + kWave - 1) / kWave;
 
   // the batch of one that lpa_step / lpa_run use
@@ -950,6 +958,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   h->self->capacity = 1;
   h->self->k = kernel_k(k, cfg.flags);
   h->self->rescan = (cfg.flags & LPA_RESCAN) != 0;
+  h->self->hub_shared = (cfg.flags & LPA_HUB_SHARED) != 0;
   h->self->async_mode = h->async_mode;
   h->self->stream = h->stream;
   h->self->check_every = h->check_every;
@@ -1019,6 +1028,7 @@ int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **
   b->capacity = capacity;
   b->k = kernel_k(k, cfg.flags);
   b->rescan = (cfg.flags & LPA_RESCAN) != 0;
+  b->hub_shared = (cfg.flags & LPA_HUB_SHARED) != 0;
   b->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   b->stream = (hipStream_t)cfg.stream;
   b->check_every = cfg.check_every;

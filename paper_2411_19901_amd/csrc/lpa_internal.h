@@ -68,6 +68,7 @@ struct GraphDesc {
   int32_t *part_key;         // [n_seg * k]
   float *part_val;           // [n_seg * k]
   int32_t *hub_cand;         // [n_hubs * k] double-scan candidates (-1: none)
+  int32_t hub_shared;        // 1: hubs use one shared sketch each (LPA_HUB_SHARED)
   unsigned long long *dN;       // [max_iter] changed vertices per iteration
   unsigned long long *scanned;  // [max_iter] CSR entries scanned per iteration
   GraphStatus *st;
@@ -117,13 +118,16 @@ struct MoveArgs {
 
 // Kernel selector: k slots of the weighted Misra-Gries sketch, or 0 for the
 // one-candidate vote of Algorithm 3 (LPA_RULE_BM_PAPER); rescan selects
-// the double scan (LPA_RESCAN, k > 0 only).
+// the double scan (LPA_RESCAN, k > 0 only); hub_shared replaces the hub
+// segments' partial sketches by one shared sketch per hub (LPA_HUB_SHARED,
+// async, k > 0, no double scan).
 // Enqueue one iteration of every graph in the launch (async: hub flag
 // snapshot, k_move, hub merge, and for the double scan the hub re-weighting
 // and decision; det: k_move; then the convergence test).  Non-null events
 // are recorded around k_move only.
-hipError_t launch_iteration(int k, bool async_mode, bool rescan, const Launch &L, int grid,
-                            int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
+hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared, const Launch &L,
+                            int grid, int merge_grid, hipStream_t s, hipEvent_t ev_beg,
+                            hipEvent_t ev_end);
 int move_blocks_per_cu(int k, bool async_mode, bool rescan);
 
 // Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read

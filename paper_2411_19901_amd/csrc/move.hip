@@ -595,7 +595,7 @@ __device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
   a.n_hubs = d.n_hubs;
   a.n_lane = d.n_lane;
   a.seg_len = d.seg_len;
-  a.n_seg = d.n_seg;
+  a.n_seg = d.hub_shared ? 0 : d.n_seg;  // shared hubs: no segment units in k_move
   a.seg_hub = d.seg_hub;
   a.hub_pbase = d.hub_pbase;
   a.hub_act = d.hub_act;
@@ -973,6 +973,96 @@ __global__ __launch_bounds__(kBlock) void k_hub_mark(Launch L) {
   }
 }
 
+// LPA_HUB_SHARED (ablation of Section 4.3's partial sketches): one workgroup
+// per active hub feeds all of the hub's entries into a single sketch in
+// LDS that its 256 threads update concurrently with LDS atomics, in the
+// manner of the shared mode of Algorithm 5: add to a matching slot, else
+// claim a free slot by compare-and-swap (retry if another thread took it),
+// else subtract from every slot (by d = min(w, smallest slot), then place
+// the residue).  Updates race, so the sketch is approximate; every retry
+// loop is bounded.  The hub then takes the heaviest slot.
+template <int K>
+__device__ __forceinline__ void shared_add(int *key, float *val, int c, float w) {
+  for (int attempt = 0; attempt < 2 * K + 2 && w > 0.0f; ++attempt) {
+    int hit = -1, freeslot = -1;
+    float seen = 0.0f, m = w;
+#pragma unroll
+    for (int s = 0; s < K; ++s) {
+      const float vs = __hip_atomic_load(&val[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const int ks = __hip_atomic_load(&key[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (ks == c && vs > 0.0f && hit < 0) hit = s;
+      if (!(vs > 0.0f) && freeslot < 0) {
+        freeslot = s;
+        seen = vs;
+      }
+      m = fminf(m, vs);
+    }
+    if (hit >= 0) {
+      atomicAdd(&val[hit], w);
+      return;
+    }
+    if (freeslot >= 0) {
+      const unsigned want = __float_as_uint(seen);
+      if (atomicCAS((unsigned *)&val[freeslot], want, __float_as_uint(w)) == want) {
+        __hip_atomic_store(&key[freeslot], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        return;
+      }
+      continue;  // another thread took the slot: look again
+    }
+    if (m > 0.0f) {
+#pragma unroll
+      for (int s = 0; s < K; ++s) atomicAdd(&val[s], -m);
+    }
+    w -= m;  // the residue, if any, looks for a slot that just emptied
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_hub_shared(Launch L) {
+  __shared__ int key[K];
+  __shared__ float val[K];
+  for (int item = blockIdx.x; item < L.total_hubs; item += gridDim.x) {
+    const int g = find_graph(L.prefix_hubs, L.G, item);
+    const GraphDesc &gd = L.d[g];
+    if (gd.st->done) continue;
+    const MoveArgs a = make_args(gd, gd.st->iter);
+    const int h = item - L.prefix_hubs[g];
+    if (a.hub_act[h] == 0) continue;
+    const int v = a.order[h];
+    if (threadIdx.x < K) {
+      key[threadIdx.x] = -1;
+      val[threadIdx.x] = 0.0f;
+    }
+    __syncthreads();
+    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
+    for (int e = rb + (int)threadIdx.x; e < re; e += blockDim.x) {
+      const int j = __builtin_nontemporal_load(a.col + e);
+      if (j == v) continue;
+      const float w = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
+      shared_add<K>(key, val, a.C[j], w);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int cv = a.C[v];
+      int c = cv;
+      float bv = 0.0f;
+      for (int s = 0; s < K; ++s)
+        if (val[s] > bv || (val[s] == bv && val[s] > 0.0f && key[s] < c)) {
+          c = key[s];
+          bv = val[s];
+        }
+      const bool moved = c != cv && (!a.pickless || c < cv);
+      if (moved) {
+        a.C[v] = c;
+        atomicAdd(gd.dN + gd.st->iter, 1ull);
+      }
+      a.hub_act[h] = moved ? 1 : 0;  // k_hub_mark flags the neighbours
+      atomicAdd(gd.scanned + gd.st->iter, (unsigned long long)(re - rb));
+    }
+    __syncthreads();
+  }
+}
+
 // Convergence test of Algorithm 1 for every graph of the launch: after
 // iteration l, stop when l is not a pick-less iteration and dN / N < tol,
 // or when max_iter iterations have run.
@@ -997,7 +1087,7 @@ __global__ void k_finish(Launch L) {
 }
 
 // ---------------------------------------------------------------------------
-template <int K, bool ASYNC, bool RS>
+template <int K, bool ASYNC, bool RS, bool HS = false>
 static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_t s,
                            hipEvent_t ev_beg, hipEvent_t ev_end) {
   hipError_t e = hipSuccess;
@@ -1013,7 +1103,13 @@ static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_
       hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, L);
   }
   if (ev_end && (e = hipEventRecord(ev_end, s)) != hipSuccess) return e;
-  if (ASYNC && L.total_merge > 0) {
+  if constexpr (HS) {  // shared hub sketches replace segments and merging
+    if (L.total_hubs > 0) {
+      const int hg = L.total_hubs < grid * 4 ? L.total_hubs : grid * 4;
+      hipLaunchKernelGGL((k_hub_shared<K>), dim3(hg), dim3(256), 0, s, L);
+      if (L.total_segs > 0) hipLaunchKernelGGL(k_hub_mark, dim3(grid), dim3(kBlock), 0, s, L);
+    }
+  } else if (ASYNC && L.total_merge > 0) {
     if constexpr (RS) {
       hipLaunchKernelGGL((k_hub_cand<K>), dim3(merge_grid), dim3(kBlock), 0, s, L);
       if (L.total_segs > 0)
@@ -1068,8 +1164,27 @@ static int occ_mode(int k) {
   }
 }
 
-hipError_t launch_iteration(int k, bool async_mode, bool rescan, const Launch &L, int grid,
-                            int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
+template <bool HS>
+static hipError_t launch_hs(int k, const Launch &L, int grid, int merge_grid, hipStream_t s,
+                            hipEvent_t b, hipEvent_t e) {
+  switch (k) {
+    case 1: return launch_t<1, true, false, HS>(L, grid, merge_grid, s, b, e);
+    case 2: return launch_t<2, true, false, HS>(L, grid, merge_grid, s, b, e);
+    case 4: return launch_t<4, true, false, HS>(L, grid, merge_grid, s, b, e);
+    case 8: return launch_t<8, true, false, HS>(L, grid, merge_grid, s, b, e);
+    case 16: return launch_t<16, true, false, HS>(L, grid, merge_grid, s, b, e);
+    case 32: return launch_t<32, true, false, HS>(L, grid, merge_grid, s, b, e);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared, const Launch &L,
+                            int grid, int merge_grid, hipStream_t s, hipEvent_t ev_beg,
+                            hipEvent_t ev_end) {
+  if (hub_shared) {  // async sketch rule without double scan only
+    if (!async_mode || rescan || k == 0) return hipErrorInvalidValue;
+    return launch_hs<true>(k, L, grid, merge_grid, s, ev_beg, ev_end);
+  }
   if (k == 0) {  // the vote of Algorithm 3 (no double scan)
     if (rescan) return hipErrorInvalidValue;
     return async_mode ? launch_t<0, true, false>(L, grid, merge_grid, s, ev_beg, ev_end)

@@ -34,6 +34,7 @@ LPA_MODE_ASYNC = 1
 LPA_VALIDATE = 0x100
 LPA_RULE_BM_PAPER = 0x200
 LPA_RESCAN = 0x400
+LPA_HUB_SHARED = 0x800
 
 MODES = {"det": LPA_MODE_DET, "async": LPA_MODE_ASYNC}
 # per-vertex rule: the k-slot weighted Misra-Gries sketch, or the
@@ -305,7 +306,8 @@ class LPA:
     def __init__(self, row_ptr, col, weights=None, k: int = 8, tol: float = 0.05,
                  max_iter: int = 20, seed: int = 0, mode: str = "det", rho: int = 8,
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
-                 stream=None, workspace=None, rule: str = "mg", rescan: bool = False):
+                 stream=None, workspace=None, rule: str = "mg", rescan: bool = False,
+                 hub_shared: bool = False):
         import torch
 
         def usable(t):  # device memory, or pinned host memory the device maps
@@ -325,7 +327,7 @@ class LPA:
                        else torch.device("cuda", torch.cuda.current_device()))
         cfg = lpa_config_default()
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
-                     | (LPA_RESCAN if rescan else 0))
+                     | (LPA_RESCAN if rescan else 0) | (LPA_HUB_SHARED if hub_shared else 0))
         cfg.rho = rho
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -426,10 +428,12 @@ class Batch:
     iteration (see lpa_batch_create in include/lpa.h)."""
 
     def __init__(self, capacity: int, k: int = 8, mode: str = "det", check_every: int = 0,
-                 stream=None, device=None, rule: str = "mg", rescan: bool = False):
+                 stream=None, device=None, rule: str = "mg", rescan: bool = False,
+                 hub_shared: bool = False):
         import torch
         cfg = lpa_config_default()
-        cfg.flags = MODES[mode] | RULES[rule] | (LPA_RESCAN if rescan else 0)
+        cfg.flags = (MODES[mode] | RULES[rule] | (LPA_RESCAN if rescan else 0)
+                     | (LPA_HUB_SHARED if hub_shared else 0))
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream

@@ -105,9 +105,18 @@ def test_bm_paper_rule_flag():
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
     assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
-    cfg.flags = lpa.LPA_MODE_DET | 0x800
+    cfg.flags = lpa.LPA_MODE_DET | 0x1000
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_UNSUPPORTED
+    # one shared sketch per hub: async sketch rule without double scan only
+    for bad in (lpa.LPA_MODE_DET | lpa.LPA_HUB_SHARED,
+                lpa.LPA_MODE_ASYNC | lpa.LPA_HUB_SHARED | lpa.LPA_RESCAN,
+                lpa.LPA_MODE_ASYNC | lpa.LPA_HUB_SHARED | lpa.LPA_RULE_BM_PAPER):
+        cfg.flags = bad
+        assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+            lpa.LPA_ERR_ARG
+    cfg.flags = lpa.LPA_MODE_ASYNC | lpa.LPA_HUB_SHARED
+    assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
     # the double scan needs the sketch rule
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER | lpa.LPA_RESCAN
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG

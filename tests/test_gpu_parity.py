@@ -401,3 +401,31 @@ def test_rescan_batch_and_rejections():
     assert ei.value.code == lpa.LPA_ERR_ARG
     for x in solvers + [single, batch]:
         x.close()
+
+
+# ---- one shared sketch per hub (LPA_HUB_SHARED, ablation of Section 4.3) --
+
+@pytest.mark.parametrize("lane_max", [0, 64])
+def test_hub_shared_validity(lane_max):
+    # lane_max 64 sends every vertex above 64 through the shared-sketch
+    # workgroups; results race, so check validity, counters and quality
+    for name in ("rmat14-w", "sbm1-s1", "star5000"):
+        g = graph(name)
+        rp, col, w = to_dev(g)
+        s = lpa.LPA(rp, col, w, k=8, mode="async", hub_shared=True, lane_max_degree=lane_max)
+        it = s.run()
+        lab = s.labels(device=False)
+        assert 1 <= it <= 20
+        assert lab.min() >= 0 and lab.max() < g.n
+        dn, sc = s.trace()
+        assert sc[0] == g.nnz  # every entry scanned once in the first iteration
+        q = s.modularity()
+        assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, lab)) <= 1e-9
+        if name == "sbm1-s1":
+            q_exact = oracle.modularity(g.row_ptr, g.col, None,
+                                        oracle.lpa_run(g.row_ptr, g.col, None, k=0)[0])
+            assert q > 0.9 * q_exact, (q, q_exact)
+        s.close()
+    with pytest.raises(lpa.LpaError):
+        rp, col, w = to_dev(graph("sbm1-s1"))
+        lpa.LPA(rp, col, w, k=8, mode="det", hub_shared=True)
