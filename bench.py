@@ -378,7 +378,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "design is described in DESIGN.md but not built", file=sys.stderr)
+              "path is not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

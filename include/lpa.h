@@ -24,7 +24,7 @@
  *                   are merged (Section 4.3).  Results depend on scheduling.
  *
  * Readings of points the paper leaves open (shared with the CPU
- * definition; listed in the design doc): the sketch decrement subtracts
+ * definition): the sketch decrement subtracts
  * d = min(w, smallest slot) and inserts the residue w - d (identical to the
  * paper's rule on unit weights); k = 1 is the same rule with one slot;
  * ties go to the lowest label; an empty sketch keeps the label; a vertex

@@ -15,7 +15,7 @@
  *   - changed vertices mark their neighbours unprocessed (Algorithm 1);
  *   - stop when not pick-less and dN/N < tau, or after max_iter.
  *
- * Readings of points the paper leaves open (each is listed in the design doc):
+ * Readings of points the paper leaves open:
  *   R1 decrement: when no slot is free the paper subtracts w from every slot
  *      (Section 4.1, Algorithm 2).  On non-unit weights that drives slots
  *      negative, so they can never become empty again.  We use the

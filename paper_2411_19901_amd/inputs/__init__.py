@@ -162,6 +162,23 @@ def with_uniform_weights(g: Graph, seed: int) -> Graph:
     return Graph(g.row_ptr, g.col, weights_uniform(g, seed), g.name + "-wU")
 
 
+def permuted(g: Graph, seed: int) -> Graph:
+    """The same graph with vertex ids relabelled by a seeded random
+    permutation (rows re-sorted, weights kept on their edges): the
+    locality-free copy of a generator whose ids carry structure."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(g.n).astype(np.int64)  # old id -> new id
+    src = np.repeat(perm, np.diff(g.row_ptr))
+    dst = perm[g.col.astype(np.int64)]
+    order = np.argsort(src * g.n + dst, kind="stable")
+    rp = np.zeros(g.n + 1, np.int64)
+    np.add.at(rp, perm + 1, np.diff(g.row_ptr))
+    rp = np.cumsum(rp).astype(np.int32)
+    col = dst[order].astype(np.int32)
+    w = g.w[order] if g.w is not None else None
+    return Graph(rp, col, w, g.name + "-perm")
+
+
 def from_edges(n: int, edges, name: str = "edges") -> Graph:
     """Tiny helper: symmetric CSR from an undirected edge list (Python)."""
     adj = [set() for _ in range(n)]

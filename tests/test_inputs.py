@@ -73,3 +73,20 @@ def test_two_cliques(gen):
     g = gen.two_cliques(4)
     check_csr(g)
     assert g.nnz == 2 * (4 * 3 + 1)
+
+
+def test_permuted_is_isomorphic():
+    from paper_2411_19901_amd import inputs
+    g = inputs.with_uniform_weights(inputs.rmat(10), 3)
+    h = inputs.permuted(g, 7)
+    assert h.n == g.n and h.nnz == g.nnz
+    assert np.all(np.diff(h.row_ptr) >= 0)
+    # rows sorted, symmetric, degree multiset and weight multiset kept
+    for i in range(h.n):
+        r = h.col[h.row_ptr[i]:h.row_ptr[i + 1]]
+        assert np.all(np.diff(r) > 0)
+    assert sorted(np.diff(g.row_ptr)) == sorted(np.diff(h.row_ptr))
+    assert np.array_equal(np.sort(g.w), np.sort(h.w))
+    edges = {(i, int(j)): float(x) for i in range(h.n)
+             for j, x in zip(h.col[h.row_ptr[i]:h.row_ptr[i + 1]], h.w[h.row_ptr[i]:h.row_ptr[i + 1]])}
+    assert all(edges[(j, i)] == x for (i, j), x in edges.items())
