@@ -105,6 +105,14 @@ typedef enum lpa_status {
  * of per-segment sketches merged afterwards.  Updates race, so results are
  * approximate and depend on scheduling. */
 #define LPA_HUB_SHARED 0x800u
+/* Run iterations from a captured hipGraph: when check_every is 0, the
+ * remaining iterations of an lpa_run / lpa_batch_run (all their kernels)
+ * are captured once on a private stream of the handle or batch and the
+ * graph is replayed on the caller's stream; it is captured again only when
+ * the launch shape (graphs, work items, iteration count) changes.  Results
+ * are identical to launching the kernels one by one.  Ignored while
+ * per-iteration profiling (lpa_profile) is on. */
+#define LPA_CAPTURE 0x1000u
 
 /* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji). */
 typedef struct lpa_graph {
@@ -117,7 +125,7 @@ typedef struct lpa_graph {
 typedef struct lpa_config {
   uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC,
                               | LPA_VALIDATE, | LPA_RULE_BM_PAPER, | LPA_RESCAN,
-                              | LPA_HUB_SHARED */
+                              | LPA_HUB_SHARED, | LPA_CAPTURE */
   int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per

@@ -304,6 +304,11 @@ struct lpa_batch {
   int k = 8;  // kernel selector: sketch slots, 0 = the vote of Algorithm 3
   bool rescan = false;      // double scan (LPA_RESCAN)
   bool hub_shared = false;  // one shared sketch per hub (LPA_HUB_SHARED)
+  bool capture = false;     // replay iterations from a captured hipGraph (LPA_CAPTURE)
+  hipStream_t cap_stream = nullptr;  // private stream the iterations are captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  long long graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   bool async_mode = false;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -579,12 +584,19 @@ int batch_alloc(lpa_batch *b) {
   if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return LPA_ERR_HIP;
   b->grid_cap = b->cus * move_blocks_per_cu(b->k, b->async_mode, b->rescan);
+  if (b->capture && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return LPA_ERR_HIP;
+  }
   return LPA_OK;
 }
 
 void batch_release(lpa_batch *b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->stream);
+  if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->dblock) (void)hipFree(b->dblock);
   if (b->hblock) (void)hipHostFree(b->hblock);
   delete b;
@@ -679,6 +691,38 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
   int mg = (b->total_merge + waves_per_block - 1) / waves_per_block;
   if (mg > b->cus * 4) mg = b->cus * 4;
   if (mg < 1) mg = 1;
+  const bool profiling = prof && !prof->ev_beg.empty();
+  if (b->capture && b->check_every == 0 && !profiling) {
+    // every remaining iteration as one hipGraph, captured on a private
+    // stream once per launch shape and replayed on the caller's stream
+    // (the descriptor table it reads is uploaded before each replay)
+    const long long key[8] = {iters, grid, mg, L.G, L.total_items, L.total_hubs, L.total_merge,
+                              L.total_segs};
+    if (!b->graph_exec || memcmp(key, b->graph_key, sizeof(key)) != 0) {
+      if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
+      b->graph_exec = nullptr;
+      b->graph = nullptr;
+      HIP_TRY_B(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->cap_stream, b->d_finished, 1);
+      hipError_t e = hipSuccess;
+      for (int i = 0; i < iters && e == hipSuccess; ++i)
+        e = launch_iteration(b->k, b->async_mode, b->rescan, b->hub_shared, L, grid, mg,
+                             b->cap_stream, nullptr, nullptr);
+      hipGraph_t g = nullptr;
+      const hipError_t ee = hipStreamEndCapture(b->cap_stream, &g);
+      if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail_hip_b(b, e, "iteration capture");
+      }
+      HIP_TRY_B(b, ee);
+      b->graph = g;
+      HIP_TRY_B(b, hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+      memcpy(b->graph_key, key, sizeof(key));
+    }
+    HIP_TRY_B(b, hipGraphLaunch(b->graph_exec, b->stream));
+    return LPA_OK;
+  }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->stream, b->d_finished, 1);
   for (int i = 0; i < iters; ++i) {
     hipEvent_t eb = nullptr, ee = nullptr;
@@ -763,7 +807,8 @@ static int check_config(const lpa_config &cfg) {
   const uint32_t mode = cfg.flags & LPA_MODE_MASK;
   if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
   if ((cfg.flags &
-       ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN | LPA_HUB_SHARED)) != 0)
+       ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN | LPA_HUB_SHARED |
+         LPA_CAPTURE)) != 0)
     return LPA_ERR_UNSUPPORTED;
   if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
   return LPA_OK;
@@ -959,6 +1004,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   h->self->k = kernel_k(k, cfg.flags);
   h->self->rescan = (cfg.flags & LPA_RESCAN) != 0;
   h->self->hub_shared = (cfg.flags & LPA_HUB_SHARED) != 0;
+  h->self->capture = (cfg.flags & LPA_CAPTURE) != 0;
   h->self->async_mode = h->async_mode;
   h->self->stream = h->stream;
   h->self->check_every = h->check_every;
@@ -1029,6 +1075,7 @@ int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **
   b->k = kernel_k(k, cfg.flags);
   b->rescan = (cfg.flags & LPA_RESCAN) != 0;
   b->hub_shared = (cfg.flags & LPA_HUB_SHARED) != 0;
+  b->capture = (cfg.flags & LPA_CAPTURE) != 0;
   b->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   b->stream = (hipStream_t)cfg.stream;
   b->check_every = cfg.check_every;

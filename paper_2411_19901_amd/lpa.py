@@ -35,6 +35,7 @@ LPA_VALIDATE = 0x100
 LPA_RULE_BM_PAPER = 0x200
 LPA_RESCAN = 0x400
 LPA_HUB_SHARED = 0x800
+LPA_CAPTURE = 0x1000
 
 MODES = {"det": LPA_MODE_DET, "async": LPA_MODE_ASYNC}
 # per-vertex rule: the k-slot weighted Misra-Gries sketch, or the
@@ -307,7 +308,7 @@ class LPA:
                  max_iter: int = 20, seed: int = 0, mode: str = "det", rho: int = 8,
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
                  stream=None, workspace=None, rule: str = "mg", rescan: bool = False,
-                 hub_shared: bool = False):
+                 hub_shared: bool = False, capture: bool = False):
         import torch
 
         def usable(t):  # device memory, or pinned host memory the device maps
@@ -327,7 +328,8 @@ class LPA:
                        else torch.device("cuda", torch.cuda.current_device()))
         cfg = lpa_config_default()
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
-                     | (LPA_RESCAN if rescan else 0) | (LPA_HUB_SHARED if hub_shared else 0))
+                     | (LPA_RESCAN if rescan else 0) | (LPA_HUB_SHARED if hub_shared else 0)
+                     | (LPA_CAPTURE if capture else 0))
         cfg.rho = rho
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -429,11 +431,11 @@ class Batch:
 
     def __init__(self, capacity: int, k: int = 8, mode: str = "det", check_every: int = 0,
                  stream=None, device=None, rule: str = "mg", rescan: bool = False,
-                 hub_shared: bool = False):
+                 hub_shared: bool = False, capture: bool = False):
         import torch
         cfg = lpa_config_default()
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_RESCAN if rescan else 0)
-                     | (LPA_HUB_SHARED if hub_shared else 0))
+                     | (LPA_HUB_SHARED if hub_shared else 0) | (LPA_CAPTURE if capture else 0))
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream

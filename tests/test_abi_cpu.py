@@ -105,7 +105,7 @@ def test_bm_paper_rule_flag():
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
     assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
-    cfg.flags = lpa.LPA_MODE_DET | 0x1000
+    cfg.flags = lpa.LPA_MODE_DET | 0x2000
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_UNSUPPORTED
     # one shared sketch per hub: async sketch rule without double scan only
