@@ -171,7 +171,8 @@ def bench_batch(args):
                        stream=stream) for g in gs]
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t
-    batch = lpa.Batch(len(solvers), k=args.k, mode=args.mode, stream=stream)
+    batch = lpa.Batch(len(solvers), k=args.k, mode=args.mode, stream=stream,
+                      capture=args.capture)
 
     def digest():
         h = hashlib.sha256()
@@ -185,8 +186,7 @@ def bench_batch(args):
             s.run()
 
     def batched():
-        for s in solvers:
-            s.reset()
+        batch.reset(solvers)
         batch.run(solvers)
 
     timings = {}
@@ -211,7 +211,9 @@ def bench_batch(args):
         "scaling": "strong", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"sbm-batch{len(gs)}-{args.mode}-k{args.k}", "graphs": len(gs),
                    "vertices": nv, "nnz": ne, "k": args.k, "mode": args.mode,
-                   "step": "reset every handle + lpa_batch_run over all of them"},
+                   "captured": bool(args.capture),
+                   "step": "lpa_batch_reset + lpa_batch_run over all of them (solo: lpa_reset + "
+                           "lpa_run per graph)"},
         "solo_graphs_per_s": round(len(gs) / timings["solo"], 2),
         "solo_ms_per_step": round(timings["solo"] * 1e3, 3),
         "speedup_vs_solo": round(timings["solo"] / timings["batched"], 3),
@@ -335,6 +337,8 @@ def main():
     ap.add_argument("--host-csr", action="store_true",
                     help="keep row_ptr / col / weights in pinned host memory (the kernels read "
                          "them over the host link; only the O(|V|) state is in device memory)")
+    ap.add_argument("--capture", action="store_true",
+                    help="batch workload: replay the iterations from a captured hipGraph")
     ap.add_argument("--hub-shared", action="store_true",
                     help="one shared LDS sketch per high-degree vertex instead of merged "
                          "partial sketches (async ablation)")

@@ -227,6 +227,11 @@ int lpa_batch_step(lpa_batch *b, lpa_handle *const *hs, int count, int64_t *chan
  * max_iter; synchronises.  *iterations = the largest iteration count. */
 int lpa_batch_run(lpa_batch *b, lpa_handle *const *hs, int count, int *iterations);
 
+/* lpa_reset of every handle in hs[0..count) with one kernel launch
+ * (labels to vertex ids, all vertices unprocessed, counters cleared), for
+ * handles that fit the batch as in lpa_batch_run; does not synchronise. */
+int lpa_batch_reset(lpa_batch *b, lpa_handle *const *hs, int count);
+
 /* Release the batch (not its handles).  NULL is accepted. */
 int lpa_batch_free(lpa_batch *b);
 

@@ -240,6 +240,33 @@ __global__ void k_status_set(GraphStatus *st, int iter, int done) {
   }
 }
 
+// lpa_reset of every graph of a table: blockIdx.y (strided) picks the graph,
+// the x blocks stride over its vertices; block x = 0 also clears the
+// per-iteration counters and the status.
+__global__ void k_batch_reset(const GraphDesc *d, int G) {
+  for (int g = blockIdx.y; g < G; g += gridDim.y) {
+    const GraphDesc &gd = d[g];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < gd.n; i += gridDim.x * blockDim.x) {
+      gd.C[0][i] = i;
+      if (gd.C[1] != gd.C[0]) gd.C[1][i] = i;
+      gd.act[0][i] = 1;
+      if (gd.act[1] != gd.act[0]) gd.act[1][i] = 0;
+    }
+    if (blockIdx.x == 0) {
+      const int T = gd.max_iter > 0 ? gd.max_iter : 1;
+      for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        gd.dN[t] = 0;
+        gd.scanned[t] = 0;
+      }
+      if (threadIdx.x == 0) {
+        gd.st->iter = 0;
+        gd.st->done = (gd.n == 0 || gd.max_iter == 0) ? 1 : 0;
+        gd.st->err = 0;
+      }
+    }
+  }
+}
+
 __global__ void k_status_clear_err(GraphStatus *st) {
   if (threadIdx.x == 0) st->err = 0;
 }
@@ -1084,6 +1111,26 @@ int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **
     return rc;
   }
   *out = b;
+  return LPA_OK;
+}
+
+int lpa_batch_reset(lpa_batch *b, lpa_handle *const *hs, int count) {
+  if (!b || (count > 0 && !hs)) return LPA_ERR_ARG;
+  if (b->poisoned) return LPA_ERR_HIP;
+  int rc = batch_load(b, hs, count);
+  if (rc) return batch_error_to_handles(b, rc);
+  if (count == 0) return LPA_OK;
+  int maxn = 1;
+  for (int g = 0; g < count; ++g) maxn = hs[g]->n > maxn ? hs[g]->n : maxn;
+  const int gx = grid_for((size_t)maxn, kAuxBlock, 1024);
+  const int gy = count < 65535 ? count : 65535;
+  hipLaunchKernelGGL(k_batch_reset, dim3(gx, gy), dim3(kAuxBlock), 0, b->stream, b->d_desc, count);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return batch_error_to_handles(b, fail_hip_b(b, e, "batch reset"));
+  for (int g = 0; g < count; ++g) {
+    hs[g]->iter = 0;
+    hs[g]->finished = hs[g]->n == 0 || hs[g]->max_iter == 0;
+  }
   return LPA_OK;
 }
 

@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
                                           ip]),
         "lpa_batch_run": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ip]),
         "lpa_batch_free": (ctypes.c_int, [H]),
+        "lpa_batch_reset": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
         "lpa_error_string": (ctypes.c_char_p, [ctypes.c_int]),
         "lpa_last_error": (ctypes.c_char_p, [H]),
         "lpa_pointer_location": (ctypes.c_int, [ctypes.c_void_p, ip]),
@@ -449,6 +450,11 @@ class Batch:
 
     def run(self, solvers) -> int:
         return lpa_batch_run(self.b, [s.h for s in solvers])
+
+    def reset(self, solvers) -> None:
+        """lpa_reset of every solver with one kernel launch."""
+        hs = [s.h for s in solvers]
+        _check(load().lpa_batch_reset(self.b, _handle_array(hs), len(hs)), "lpa_batch_reset")
 
     def close(self) -> None:
         if getattr(self, "b", None):

@@ -131,3 +131,27 @@ def test_workspace_handles(mode):
     with pytest.raises(lpa.LpaError) as ei:
         make_solver(g, mode=mode, workspace=too_small)
     assert ei.value.code == lpa.LPA_ERR_NOMEM
+
+
+def test_batch_reset_equals_reset():
+    gs = mixed_graphs(count=10, seed=41)
+    solvers = [make_solver(g) for g in gs]
+    batch = lpa.Batch(len(solvers), k=8, mode="det")
+    batch.run(solvers)
+    ref = [s.labels(device=False) for s in solvers]
+    for rep in range(2):
+        batch.reset(solvers)
+        for g, s in zip(gs, solvers):  # back to the initial state
+            C, act, it = s.get_state()
+            assert it == 0 and np.array_equal(C, np.arange(g.n, dtype=np.int32))
+            assert g.n == 0 or act.min() == 1
+            dn, sc = s.trace()
+            assert len(dn) == 0
+        batch.run(solvers)
+        for g, s, r in zip(gs, solvers, ref):
+            assert np.array_equal(s.labels(device=False), r), g.name
+            dn, sc = s.trace()
+            assert np.array_equal(dn, oracle_labels(g)[2]), g.name
+    batch.close()
+    for s in solvers:
+        s.close()
