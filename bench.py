@@ -337,6 +337,8 @@ def main():
     ap.add_argument("--host-csr", action="store_true",
                     help="keep row_ptr / col / weights in pinned host memory (the kernels read "
                          "them over the host link; only the O(|V|) state is in device memory)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick lane_max_degree by timing candidates on the graph (untimed)")
     ap.add_argument("--capture", action="store_true",
                     help="batch workload: replay the iterations from a captured hipGraph")
     ap.add_argument("--hub-shared", action="store_true",
@@ -420,6 +422,15 @@ def main():
     torch.cuda.synchronize()
     h2d_s = time.perf_counter() - t
     stream = torch.cuda.current_stream(dev)
+    tuned = None
+    if args.autotune:
+        from paper_2411_19901_amd import tune
+        t = time.perf_counter()
+        tuned = tune.tune(rp, col, w, k=args.k, mode=args.mode, rule=args.rule)
+        tuned["seconds"] = round(time.perf_counter() - t, 2)
+        tuned["table"] = {str(k_): round(v, 4) for k_, v in tuned["table"].items()}
+        args.lane_max_degree = tuned["lane_max_degree"]
+        log(f"[bench] autotuned lane_max_degree = {args.lane_max_degree} ({tuned['table']})")
     free0, _ = torch.cuda.mem_get_info(dev)
     t = time.perf_counter()
     solver = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
@@ -491,6 +502,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": workload, "n": g.n, "nnz": g.nnz, "k": args.k, "rule": args.rule,
+                   "lane_max_degree": args.lane_max_degree or (1024 if args.mode == "async"
+                                                                else 4096),
                    "rescan": args.rescan,
                    "mode": args.mode,
                    "tol": args.tol, "max_iter": args.max_iter, "rho": 8,
@@ -526,6 +539,9 @@ def main():
         "hipmeminfo_bytes_per_vertex": round((free0 - free1) / g.n, 3),
         "gpu": torch.cuda.get_device_name(dev),
     }
+    if tuned is not None:
+        result["autotune"] = {"lane_max_degree": tuned["lane_max_degree"],
+                              "ns_per_entry": tuned["table"], "seconds": tuned["seconds"]}
     del labels
     solver.close()
     if not args.no_cpu_baseline:

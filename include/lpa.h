@@ -130,7 +130,8 @@ typedef struct lpa_config {
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per
                               vertex, higher degrees cooperatively;
-                              0 = default for the mode.  Never changes
+                              0 = default for the mode (async 1024, det
+                              4096).  Never changes
                               LPA_MODE_DET results. */
   int32_t check_every;     /* lpa_run / lpa_batch_run read the convergence
                               state on the host every this many iterations

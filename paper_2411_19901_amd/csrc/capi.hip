@@ -494,7 +494,9 @@ int check_ready(lpa_handle *h) {
 }
 
 // Longest run of CSR entries one lane scans (measured on R-MAT scale 24).
-int default_lane_max(bool async_mode) { return async_mode ? 2048 : 1024; }
+// Lane threshold S when the caller leaves it 0: the autotuner's choice on
+// R-MAT scale 22-24 (async 1024, det 4096); tune.py picks per graph.
+int default_lane_max(bool async_mode) { return async_mode ? 1024 : 4096; }
 
 // labels after the iterations run so far
 int32_t *cur_labels(const lpa_handle *h) { return h->desc.C[h->iter & 1]; }
