@@ -655,7 +655,7 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
     unfinished += live ? 1 : 0;
     pi[g + 1] = pi[g] + (live ? move_items(h) : 0);
     ph[g + 1] = ph[g] + (live && b->async_mode ? h->desc.n_hubs : 0);
-    pm[g + 1] = pm[g] + (live && b->async_mode ? (h->desc.n_hubs + kWave - 1) / kWave : 0);
+    pm[g + 1] = pm[g] + (live && b->async_mode ? (h->desc.n_hubs + kMergeHubs - 1) / kMergeHubs : 0);
     ps[g + 1] = ps[g] + (live && b->async_mode ? h->desc.n_seg : 0);
   }
   // pad the prefixes to the table capacity so the three arrays keep their offsets

@@ -10,6 +10,9 @@ namespace lpa {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;  // threads per workgroup for the move kernels
+// Hub merge kernels: kHubLanes lanes per hub, kMergeHubs hubs per wavefront.
+constexpr int kHubLanes = 4;
+constexpr int kMergeHubs = kWave / kHubLanes;
 
 // Degree classes used to order vertices by decreasing degree.  Classes
 // 0..255 hold hubs (degree > lane_max) on a log scale with eight

@@ -697,15 +697,18 @@ __device__ __forceinline__ void record_moved_hub(const MoveArgs &a, int h, bool 
 }
 
 // Merge the partial sketches of every active hub (Section 4.3).  A wavefront
-// takes 64 hubs of one graph: hubs with at most 64 partials are merged by
-// one lane each; larger ones by the whole wavefront (lane l merges partials
-// l, l + 64, ..., then a pairwise exchange across lanes).  RS = false: the
-// hub takes the merged sketch's heaviest label.  RS = true (double scan):
-// the merged sketch's live labels are stored as the hub's candidates for
-// k_hub_rescan / k_hub_pick.
+// takes kMergeHubs hubs of one graph, kHubLanes lanes each: for a hub with
+// at most 64 partials every lane of its group merges every kHubLanes-th
+// partial (the next one's loads in flight), then the group combines its
+// sketches pairwise; larger hubs are merged by the whole wavefront (lane l
+// merges partials l, l + 64, ..., then a pairwise exchange across lanes).
+// RS = false: the hub takes the merged sketch's heaviest label.  RS = true
+// (double scan): the merged sketch's live labels are stored as the hub's
+// candidates for k_hub_rescan / k_hub_pick.
 template <int K, bool RS>
 __device__ __forceinline__ void hub_merge_body(const Launch &L) {
   const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (kHubLanes - 1);
   const int wave = rfl((blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int nwaves = gridDim.x * (kBlock / kWave);
   unsigned long long changed_w = 0, zero_lane = 0, zero_w = 0;
@@ -724,7 +727,7 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
       cdN = gd.dN + iter;
     }
     const MoveArgs a = make_args(gd, iter);
-    const int h = (item - L.prefix_merge[g]) * kWave + lane;
+    const int h = (item - L.prefix_merge[g]) * kMergeHubs + lane / kHubLanes;
     int v = -1, p0 = 0, np = 0, cv = 0;
     bool active = false;
     if (h < a.n_hubs) {
@@ -738,25 +741,55 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
     const bool small = active && np <= kWave;
     SK S;
     S.clear();
-    if (small) {
-      for (int p = p0; p < p0 + np; ++p) {
-        int pk[P];
-        float pv[P];
+    if (small && sub < np) {
+      int pk[P], nk[P];
+      float pv[P], nv[P];
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        nk[s] = a.part_key[(size_t)(p0 + sub) * P + s];
+        nv[s] = a.part_val[(size_t)(p0 + sub) * P + s];
+      }
+      for (int p = p0 + sub; p < p0 + np; p += kHubLanes) {
 #pragma unroll
         for (int s = 0; s < P; ++s) {
-          pk[s] = a.part_key[(size_t)p * P + s];
-          pv[s] = a.part_val[(size_t)p * P + s];
+          pk[s] = nk[s];
+          pv[s] = nv[s];
+        }
+        if (p + kHubLanes < p0 + np) {
+#pragma unroll
+          for (int s = 0; s < P; ++s) {
+            nk[s] = a.part_key[(size_t)(p + kHubLanes) * P + s];
+            nv[s] = a.part_val[(size_t)(p + kHubLanes) * P + s];
+          }
         }
         S.merge_from(pk, pv);
       }
-      if constexpr (RS) {
+    }
+    // combine the sketches of each lane group (every lane takes part; the
+    // groups of other hubs combine empty sketches)
+#pragma unroll 1
+    for (int off = 1; off < kHubLanes; off <<= 1) {
+      int pk[P];
+      float pv[P];
 #pragma unroll
-        for (int s = 0; s < P; ++s) gd.hub_cand[(size_t)h * P + s] = S.val[s] > 0.0f ? S.key[s] : -1;
+      for (int s = 0; s < P; ++s) {  // snapshot the partner before merging
+        pk[s] = __shfl_xor(S.key[s], off);
+        pv[s] = __shfl_xor(S.val[s], off);
+      }
+      S.merge_from(pk, pv);
+    }
+    if (small) {
+      if constexpr (RS) {
+        if (sub == 0) {
+#pragma unroll
+          for (int s = 0; s < P; ++s)
+            gd.hub_cand[(size_t)h * P + s] = S.val[s] > 0.0f ? S.key[s] : -1;
+        }
       } else {
         c = S.max_key(cv);
       }
     }
-    unsigned long long big = __ballot(active && !small);
+    unsigned long long big = __ballot(active && !small && sub == 0);
     while (big) {
       const int src = __ffsll((long long)big) - 1;
       big &= big - 1;
@@ -785,7 +818,7 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
         B.merge_from(pk, pv);
       }
       if constexpr (RS) {
-        const int bh = (item - L.prefix_merge[g]) * kWave + src;
+        const int bh = (item - L.prefix_merge[g]) * kMergeHubs + src / kHubLanes;
         if (lane == 0) {
 #pragma unroll
           for (int s = 0; s < P; ++s)
@@ -793,14 +826,14 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
         }
       } else {
         const int bc = rfl(B.max_key(bcv));
-        if (lane == src) c = bc;
+        if (lane / kHubLanes == src / kHubLanes) c = bc;
       }
     }
     if constexpr (!RS) {
       const bool moved = active && c != cv && (!a.pickless || c < cv);
-      if (moved) a.C[v] = c;
-      changed_w += (unsigned long long)__popcll(__ballot(moved));
-      record_moved_hub(a, h, moved);
+      if (moved && sub == 0) a.C[v] = c;
+      changed_w += (unsigned long long)__popcll(__ballot(moved && sub == 0));
+      if (sub == 0) record_moved_hub(a, h, moved);
     }
   }
   flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
@@ -880,6 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
   const int lane = threadIdx.x & (kWave - 1);
+  const int sub = lane & (kHubLanes - 1);
   const int wave = rfl((blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int nwaves = gridDim.x * (kBlock / kWave);
   unsigned long long changed_w = 0, zero_lane = 0, zero_w = 0;
@@ -896,7 +930,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
       cdN = gd.dN + iter;
     }
     const MoveArgs a = make_args(gd, iter);
-    const int h = (item - L.prefix_merge[g]) * kWave + lane;
+    const int h = (item - L.prefix_merge[g]) * kMergeHubs + lane / kHubLanes;
     int v = -1, p0 = 0, np = 0, cv = 0;
     bool active = false;
     if (h < a.n_hubs) {
@@ -911,10 +945,14 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
     for (int s = 0; s < K; ++s) tot[s] = 0.0f;
     const bool small = active && np <= kWave;
     if (small)
-      for (int p = p0; p < p0 + np; ++p)
+      for (int p = p0 + sub; p < p0 + np; p += kHubLanes)
 #pragma unroll
         for (int s = 0; s < K; ++s) tot[s] += a.part_val[(size_t)p * K + s];
-    unsigned long long big = __ballot(active && !small);
+#pragma unroll
+    for (int s = 0; s < K; ++s)  // add up each lane group's sums
+#pragma unroll
+      for (int off = 1; off < kHubLanes; off <<= 1) tot[s] += __shfl_xor(tot[s], off);
+    unsigned long long big = __ballot(active && !small && sub == 0);
     while (big) {
       const int src = __ffsll((long long)big) - 1;
       big &= big - 1;
@@ -929,7 +967,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
       for (int s = 0; s < K; ++s) {
 #pragma unroll
         for (int off = kWave / 2; off >= 1; off >>= 1) t[s] += __shfl_xor(t[s], off);
-        tot[s] = (lane == src) ? t[s] : tot[s];
+        tot[s] = (lane / kHubLanes == src / kHubLanes) ? t[s] : tot[s];
       }
     }
     int c = cv;
@@ -944,9 +982,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
       }
     }
     const bool moved = active && c != cv && (!a.pickless || c < cv);
-    if (moved) a.C[v] = c;
-    changed_w += (unsigned long long)__popcll(__ballot(moved));
-    record_moved_hub(a, h, moved);
+    if (moved && sub == 0) a.C[v] = c;
+    changed_w += (unsigned long long)__popcll(__ballot(moved && sub == 0));
+    if (sub == 0) record_moved_hub(a, h, moved);
   }
   flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
 }
