@@ -697,11 +697,15 @@ __device__ __forceinline__ void record_moved_hub(const MoveArgs &a, int h, bool 
 }
 
 // Merge the partial sketches of every active hub (Section 4.3).  A wavefront
-// takes kMergeHubs hubs of one graph, kHubLanes lanes each: for a hub with
-// at most 64 partials every lane of its group merges every kHubLanes-th
-// partial (the next one's loads in flight), then the group combines its
-// sketches pairwise; larger hubs are merged by the whole wavefront (lane l
-// merges partials l, l + 64, ..., then a pairwise exchange across lanes).
+// takes kMergeHubs hubs of one graph, kHubLanes lanes each.  For a hub with
+// at most 64 partials the partials are fed one by one, in segment order,
+// into a single sketch, which every lane of the group computes alike: lane
+// t of the group loads partials t, t + kHubLanes, ... (the next one's loads
+// in flight) and hands each over by a lane exchange.  Feeding every partial
+// into one sketch follows the paper's merge into the first group's sketch;
+// combining already merged sketches pairwise instead measured lower
+// modularity.  Larger hubs are merged by the whole wavefront (lane l merges
+// partials l, l + 64, ..., then a pairwise exchange across lanes).
 // RS = false: the hub takes the merged sketch's heaviest label.  RS = true
 // (double scan): the merged sketch's live labels are stored as the hub's
 // candidates for k_hub_rescan / k_hub_pick.
@@ -741,42 +745,49 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
     const bool small = active && np <= kWave;
     SK S;
     S.clear();
-    if (small && sub < np) {
-      int pk[P], nk[P];
-      float pv[P], nv[P];
+    if (small) {  // np is the same on every lane of the group
+      const int gbase = lane & ~(kHubLanes - 1);
+      int ck[P], nk[P];
+      float cw[P], nv[P];
 #pragma unroll
       for (int s = 0; s < P; ++s) {
-        nk[s] = a.part_key[(size_t)(p0 + sub) * P + s];
-        nv[s] = a.part_val[(size_t)(p0 + sub) * P + s];
+        ck[s] = -1;
+        cw[s] = 0.0f;
+        nk[s] = -1;
+        nv[s] = 0.0f;
       }
-      for (int p = p0 + sub; p < p0 + np; p += kHubLanes) {
+      if (sub < np) {
 #pragma unroll
         for (int s = 0; s < P; ++s) {
-          pk[s] = nk[s];
-          pv[s] = nv[s];
+          ck[s] = a.part_key[(size_t)(p0 + sub) * P + s];
+          cw[s] = a.part_val[(size_t)(p0 + sub) * P + s];
         }
-        if (p + kHubLanes < p0 + np) {
+      }
+      for (int b = 0; b < np; b += kHubLanes) {
+        if (b + kHubLanes + sub < np) {
 #pragma unroll
           for (int s = 0; s < P; ++s) {
-            nk[s] = a.part_key[(size_t)(p + kHubLanes) * P + s];
-            nv[s] = a.part_val[(size_t)(p + kHubLanes) * P + s];
+            nk[s] = a.part_key[(size_t)(p0 + b + kHubLanes + sub) * P + s];
+            nv[s] = a.part_val[(size_t)(p0 + b + kHubLanes + sub) * P + s];
           }
         }
-        S.merge_from(pk, pv);
-      }
-    }
-    // combine the sketches of each lane group (every lane takes part; the
-    // groups of other hubs combine empty sketches)
-#pragma unroll 1
-    for (int off = 1; off < kHubLanes; off <<= 1) {
-      int pk[P];
-      float pv[P];
+        const int nt = min(kHubLanes, np - b);
+        for (int t = 0; t < nt; ++t) {
+          int pk[P];
+          float pv[P];
 #pragma unroll
-      for (int s = 0; s < P; ++s) {  // snapshot the partner before merging
-        pk[s] = __shfl_xor(S.key[s], off);
-        pv[s] = __shfl_xor(S.val[s], off);
+          for (int s = 0; s < P; ++s) {
+            pk[s] = __shfl(ck[s], gbase + t);
+            pv[s] = __shfl(cw[s], gbase + t);
+          }
+          S.merge_from(pk, pv);
+        }
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+          ck[s] = nk[s];
+          cw[s] = nv[s];
+        }
       }
-      S.merge_from(pk, pv);
     }
     if (small) {
       if constexpr (RS) {
