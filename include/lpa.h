@@ -113,19 +113,34 @@ typedef enum lpa_status {
  * are identical to launching the kernels one by one.  Ignored while
  * per-iteration profiling (lpa_profile) is on. */
 #define LPA_CAPTURE 0x1000u
+/* Ablation of the wavefront votes of Section 4.1 (LPA_MODE_DET, sketch
+ * rule, no LPA_RESCAN; LPA_ERR_ARG otherwise): in the one-wavefront-per-
+ * vertex path for vertices above lane_max_degree, whose lanes hold one
+ * sketch slot each, the lanes find the slot of a label, a free slot and the
+ * smallest slot through shared variables in LDS written with plain stores
+ * and atomic minimums (the shared-variable protocol of Algorithm 5) instead
+ * of wavefront votes.  Results are identical; only the speed differs. */
+#define LPA_SHARED_VARS 0x2000u
 
-/* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji). */
+/* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji).  Row
+ * offsets are given either as int32 (row_ptr, graphs of fewer than 2^31 - 1
+ * entries) or as int64 (row_ptr64, any size that memory holds, up to
+ * 2^62 entries): exactly one of the two is set when n > 0, otherwise
+ * lpa_init returns LPA_ERR_ARG.  With either width every vertex has fewer
+ * than 2^31 entries (checked under LPA_VALIDATE).  The arrays may be in
+ * device memory or in pinned host memory (lpa_pointer_location). */
 typedef struct lpa_graph {
   int32_t n;               /* number of vertices, 0 <= n < 2^31 - 1 */
-  int64_t nnz;             /* number of CSR entries (directed), < 2^31 */
-  const int32_t *row_ptr;  /* device int32[n+1] */
-  const int32_t *col_idx;  /* device int32[nnz], neighbour ids */
+  int64_t nnz;             /* number of CSR entries (directed) */
+  const int32_t *row_ptr;  /* int32[n+1], or NULL when row_ptr64 is set */
+  const int32_t *col_idx;  /* int32[nnz], neighbour ids */
+  const int64_t *row_ptr64; /* int64[n+1], or NULL when row_ptr is set */
 } lpa_graph;
 
 typedef struct lpa_config {
   uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC,
                               | LPA_VALIDATE, | LPA_RULE_BM_PAPER, | LPA_RESCAN,
-                              | LPA_HUB_SHARED, | LPA_CAPTURE */
+                              | LPA_HUB_SHARED, | LPA_CAPTURE, | LPA_SHARED_VARS */
   int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per
@@ -188,7 +203,10 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol,
 
 /* Device bytes lpa_init needs for a graph of n vertices and nnz entries
  * with these parameters (cfg NULL = defaults); the size of a caller
- * workspace (lpa_config.workspace). */
+ * workspace (lpa_config.workspace).  The size does not depend on the
+ * width of the row offsets.  LPA_ERR_ARG for nnz < 0 or nnz >= 2^62;
+ * LPA_ERR_UNSUPPORTED when LPA_MODE_ASYNC would split the hubs into 2^30
+ * or more segments (nnz / lane_max_degree too large: raise the threshold). */
 int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter,
                         const lpa_config *cfg, size_t *bytes);
 
@@ -214,7 +232,11 @@ int lpa_run(lpa_handle *h, int *iterations);
  * (bit-identical labels in LPA_MODE_DET).  The handles passed to one call
  * must share k, mode, device and stream with the batch, appear once, and
  * number at most `capacity`; the set may change between calls (continuous
- * batching).  The batch owns only its launch tables.
+ * batching).  Graphs with int32 and int64 row offsets may be mixed (the
+ * launch then computes CSR positions in 64 bits for all of them).  A call
+ * whose graphs together have 2^31 or more work items (hub segments plus
+ * wavefronts of lane vertices) returns LPA_ERR_UNSUPPORTED; split it.
+ * The batch owns only its launch tables.
  *   cfg: mode flags, stream and check_every are used (NULL = defaults). */
 int lpa_batch_create(int capacity, int k, const lpa_config *cfg, lpa_batch **out);
 

@@ -44,14 +44,16 @@ __global__ void k_normalize_u8(uint8_t *p, int n) {
 }
 
 // bad |= 1: row_ptr; 2: col out of range; 4: weight not finite or <= 0
-__global__ void k_validate(int n, int64_t nnz, const int32_t *rp, const int32_t *col,
-                           const float *w, int *bad) {
+__global__ void k_validate(int n, int64_t nnz, RowPtr rp, const int32_t *col, const float *w,
+                           int *bad) {
   const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   int b = 0;
-  if (tid == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) b |= 1;
-  for (size_t i = tid; i < (size_t)n; i += stride)
-    if (rp[i] > rp[i + 1]) b |= 1;
+  if (tid == 0 && (rp[0] != 0 || rp[n] != nnz)) b |= 1;
+  for (size_t i = tid; i < (size_t)n; i += stride) {
+    const long long d = rp[i + 1] - rp[i];
+    if (d < 0 || d > (long long)INT32_MAX) b |= 1;
+  }
   for (size_t e = tid; e < (size_t)nnz; e += stride) {
     const int j = col[e];
     if (j < 0 || j >= n) b |= 2;
@@ -81,16 +83,20 @@ __global__ void k_check_labels(const int32_t *lab, int n, int *bad) {
 //      which is each block's first position for each class;
 //   3. k_bin_place: every block walks its ids in order and writes each
 //      vertex at its class's next position.
+// Largest graph: 2^62 CSR entries; async hub segments (work items of one
+// iteration) below 2^30 so that per-launch sums stay within int32.
+constexpr int64_t kMaxEntries = (int64_t)1 << 62;
+constexpr int64_t kMaxSegs = (int64_t)1 << 30;
 constexpr int kBinIds = 4096;
 constexpr int kScanChunk = 4096;  // entries per block of the prefix sum
 
-__global__ void k_bin_count(int n, const int32_t *rp, int lane_max, int nblk, unsigned *counts) {
+__global__ void k_bin_count(int n, RowPtr rp, int lane_max, int nblk, unsigned *counts) {
   __shared__ unsigned cnt[kClasses];
   for (int c = threadIdx.x; c < kClasses; c += blockDim.x) cnt[c] = 0;
   __syncthreads();
   const int v0 = blockIdx.x * kBinIds;
   for (int v = v0 + threadIdx.x; v < v0 + kBinIds && v < n; v += blockDim.x) {
-    const int d = rp[v + 1] - rp[v];
+    const int d = (int)(rp[v + 1] - rp[v]);
     if (d > 0) atomicAdd(&cnt[degree_class(d, lane_max)], 1u);
   }
   __syncthreads();
@@ -154,7 +160,7 @@ __global__ void k_scan_add(unsigned *x, size_t count, const unsigned *sums) {
 // Place every vertex of block b at its class's next position, in id order.
 // 256 threads walk the block's ids 256 at a time; the four wavefronts take
 // turns so that lower ids are placed first.
-__global__ __launch_bounds__(256) void k_bin_place(int n, const int32_t *rp, int lane_max, int nblk,
+__global__ __launch_bounds__(256) void k_bin_place(int n, RowPtr rp, int lane_max, int nblk,
                                                    const unsigned *offsets, int32_t *order) {
   __shared__ unsigned next[kClasses];
   for (int c = threadIdx.x; c < kClasses; c += blockDim.x) next[c] = 0;
@@ -166,7 +172,7 @@ __global__ __launch_bounds__(256) void k_bin_place(int n, const int32_t *rp, int
     const int v = v0 + r + (int)threadIdx.x;
     int cls = -1;
     if (v < n) {
-      const int d = rp[v + 1] - rp[v];
+      const int d = (int)(rp[v + 1] - rp[v]);
       if (d > 0) cls = degree_class(d, lane_max);
     }
     for (int w = 0; w < 4; ++w) {
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(256) void k_bin_place(int n, const int32_t *rp, int
 // --- iteration epilogue ------------------------------------------------------
 // Async hub segments: pbase[h] = sum over earlier hubs of ceil(deg / S);
 // pbase[n_hubs] (also written to *total) = number of segments.  One block.
-__global__ void k_hub_plan(const int32_t *order, int n_hubs, const int32_t *rp, int S,
+__global__ void k_hub_plan(const int32_t *order, int n_hubs, RowPtr rp, int S,
                            int32_t *pbase, int *total) {
   __shared__ long long part[1024];
   const int t = threadIdx.x, nt = blockDim.x;
@@ -215,13 +221,15 @@ __global__ void k_hub_plan(const int32_t *order, int n_hubs, const int32_t *rp, 
       part[i] = acc;
       acc += x;
     }
-    pbase[n_hubs] = (int32_t)acc;
-    *total = (int)acc;
+    // a total beyond int32 (possible only for an unvalidated invalid
+    // graph) is reported as INT32_MAX, which exceeds every segment bound
+    pbase[n_hubs] = (int32_t)(acc < INT32_MAX ? acc : INT32_MAX);
+    *total = (int)(acc < INT32_MAX ? acc : INT32_MAX);
   }
   __syncthreads();
   long long acc = part[t];
   for (int h = h0; h < h1; ++h) {
-    pbase[h] = (int32_t)acc;
+    pbase[h] = (int32_t)(acc < INT32_MAX ? acc : INT32_MAX);
     const int v = order[h];
     acc += (rp[v + 1] - rp[v] + S - 1) / S;
   }
@@ -331,17 +339,19 @@ struct lpa_batch {
   int k = 8;  // kernel selector: sketch slots, 0 = the vote of Algorithm 3
   bool rescan = false;      // double scan (LPA_RESCAN)
   bool hub_shared = false;  // one shared sketch per hub (LPA_HUB_SHARED)
+  bool shared_vars = false;  // LDS shared variables in the det hub path (LPA_SHARED_VARS)
   bool capture = false;     // replay iterations from a captured hipGraph (LPA_CAPTURE)
   hipStream_t cap_stream = nullptr;  // private stream the iterations are captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  long long graph_key[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long graph_key[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   bool async_mode = false;
   hipStream_t stream = nullptr;
   int device = 0;
   int check_every = 0;
   int cus = 1;
-  int grid_cap = 1;  // resident k_move workgroups
+  int grid_cap[2] = {1, 1};  // resident k_move workgroups: int32 / int64 positions
+  bool wide = false;         // a loaded graph has int64 row offsets
   void *dblock = nullptr;  // device: descriptors, prefixes, finished counter, status
   GraphDesc *d_desc = nullptr;
   int32_t *d_prefix = nullptr;  // items, hubs, merge items, hub segments: [cap+1] each
@@ -365,7 +375,7 @@ struct lpa_handle {
   hipStream_t stream = nullptr;
   int32_t n = 0;
   int64_t nnz = 0;
-  const int32_t *row_ptr = nullptr;
+  RowPtr row_ptr{nullptr, nullptr};
   const int32_t *col = nullptr;
   const float *w = nullptr;
   int k = 8;
@@ -481,6 +491,9 @@ int check_k(int k, uint32_t flags) {
   if ((flags & LPA_HUB_SHARED) &&
       ((flags & LPA_MODE_MASK) != LPA_MODE_ASYNC || (flags & (LPA_RULE_BM_PAPER | LPA_RESCAN))))
     return LPA_ERR_ARG;
+  if ((flags & LPA_SHARED_VARS) &&
+      ((flags & LPA_MODE_MASK) != LPA_MODE_DET || (flags & (LPA_RULE_BM_PAPER | LPA_RESCAN))))
+    return LPA_ERR_ARG;
   return LPA_OK;
 }
 
@@ -507,6 +520,7 @@ struct Layout {
   size_t st, dN, scanned, C0, C1, act0, act1, order, hist, hub_pbase, hub_act, seg_hub, pkey,
       pval, hcand, total;
   int32_t hub_cap, seg_cap, ncls;
+  bool too_many_segs;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -538,8 +552,13 @@ Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode,
     // hubs have more than S entries each; a hub of degree d > S has
     // ceil(d / S) < 2 d / S segments
     const int64_t hubs = nnz / (lane_max + 1) + 1;
+    const int64_t segs = 2 * (nnz / lane_max) + 2;
     L.hub_cap = (int32_t)(hubs < n ? hubs : n);
-    L.seg_cap = (int32_t)(2 * nnz / lane_max + 1);
+    if (segs >= kMaxSegs) {  // work items of one iteration must fit int32
+      L.too_many_segs = true;
+      return L;
+    }
+    L.seg_cap = (int32_t)segs;
     L.hub_pbase = take(((size_t)L.hub_cap + 1) * 4);
     L.hub_act = take((size_t)L.hub_cap);
     L.seg_hub = take((size_t)L.seg_cap * 4);
@@ -612,7 +631,10 @@ int batch_alloc(lpa_batch *b) {
   b->device = dev;
   if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return LPA_ERR_HIP;
-  b->grid_cap = b->cus * move_blocks_per_cu(b->k, b->async_mode, b->rescan);
+  b->grid_cap[0] = b->cus * move_blocks_per_cu(b->k, b->async_mode, b->rescan, b->shared_vars,
+                                                false);
+  b->grid_cap[1] = b->cus * move_blocks_per_cu(b->k, b->async_mode, b->rescan, b->shared_vars,
+                                                true);
   if (b->capture && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     return LPA_ERR_HIP;
@@ -640,12 +662,15 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
           *pm = b->h_prefix + 2 * (b->capacity + 1), *ps = b->h_prefix + 3 * (b->capacity + 1);
   pi[0] = ph[0] = pm[0] = ps[0] = 0;
   int unfinished = 0;
+  bool wide = false;
   for (int g = 0; g < count; ++g) {
     lpa_handle *h = hs[g];
     if (!h) return LPA_ERR_ARG;
+    wide = wide || h->row_ptr.p64 != nullptr;
     if (h->poisoned) return LPA_ERR_HIP;
     if (kernel_k(h->k, h->flags) != b->k || ((h->flags & LPA_RESCAN) != 0) != b->rescan ||
         ((h->flags & LPA_HUB_SHARED) != 0) != b->hub_shared ||
+        ((h->flags & LPA_SHARED_VARS) != 0) != b->shared_vars ||
         h->async_mode != b->async_mode || h->device != b->device || h->stream != b->stream)
       return LPA_ERR_ARG;
     for (int q = 0; q < g; ++q)
@@ -653,10 +678,17 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
     b->h_desc[g] = h->desc;
     const bool live = !h->finished;
     unfinished += live ? 1 : 0;
-    pi[g + 1] = pi[g] + (live ? move_items(h) : 0);
-    ph[g + 1] = ph[g] + (live && b->async_mode ? h->desc.n_hubs : 0);
-    pm[g + 1] = pm[g] + (live && b->async_mode ? (h->desc.n_hubs + kMergeHubs - 1) / kMergeHubs : 0);
-    ps[g + 1] = ps[g] + (live && b->async_mode ? h->desc.n_seg : 0);
+    const int64_t next[4] = {
+        (int64_t)pi[g] + (live ? move_items(h) : 0),
+        (int64_t)ph[g] + (live && b->async_mode ? h->desc.n_hubs : 0),
+        (int64_t)pm[g] + (live && b->async_mode ? (h->desc.n_hubs + kMergeHubs - 1) / kMergeHubs : 0),
+        (int64_t)ps[g] + (live && b->async_mode ? h->desc.n_seg : 0)};
+    for (int64_t x : next)  // the launch's work item numbers are int32
+      if (x > (int64_t)INT32_MAX) return LPA_ERR_UNSUPPORTED;
+    pi[g + 1] = (int32_t)next[0];
+    ph[g + 1] = (int32_t)next[1];
+    pm[g + 1] = (int32_t)next[2];
+    ps[g + 1] = (int32_t)next[3];
   }
   // pad the prefixes to the table capacity so the three arrays keep their offsets
   b->total_items = pi[count];
@@ -664,6 +696,7 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
   b->total_merge = pm[count];
   b->total_segs = ps[count];
   b->unfinished = unfinished;
+  b->wide = wide;
   b->loaded.assign(hs, hs + count);
   HIP_TRY_B(b, hipMemcpyAsync(b->d_desc, b->h_desc, (size_t)count * sizeof(GraphDesc),
                               hipMemcpyHostToDevice, b->stream));
@@ -715,7 +748,7 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
   const Launch L = make_launch(b);
   const int waves_per_block = kBlock / kWave;
   int grid = (b->total_items + waves_per_block - 1) / waves_per_block;
-  if (grid > b->grid_cap) grid = b->grid_cap;
+  if (grid > b->grid_cap[b->wide]) grid = b->grid_cap[b->wide];
   if (grid < 1) grid = 1;
   int mg = (b->total_merge + waves_per_block - 1) / waves_per_block;
   if (mg > b->cus * 4) mg = b->cus * 4;
@@ -725,8 +758,8 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
     // every remaining iteration as one hipGraph, captured on a private
     // stream once per launch shape and replayed on the caller's stream
     // (the descriptor table it reads is uploaded before each replay)
-    const long long key[8] = {iters, grid, mg, L.G, L.total_items, L.total_hubs, L.total_merge,
-                              L.total_segs};
+    const long long key[9] = {iters, grid, mg, L.G, L.total_items, L.total_hubs, L.total_merge,
+                              L.total_segs, b->wide};
     if (!b->graph_exec || memcmp(key, b->graph_key, sizeof(key)) != 0) {
       if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
       if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -736,8 +769,8 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
       hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->cap_stream, b->d_finished, 1);
       hipError_t e = hipSuccess;
       for (int i = 0; i < iters && e == hipSuccess; ++i)
-        e = launch_iteration(b->k, b->async_mode, b->rescan, b->hub_shared, L, grid, mg,
-                             b->cap_stream, nullptr, nullptr);
+        e = launch_iteration(b->k, b->async_mode, b->rescan, b->hub_shared, b->shared_vars,
+                             b->wide, L, grid, mg, b->cap_stream, nullptr, nullptr);
       hipGraph_t g = nullptr;
       const hipError_t ee = hipStreamEndCapture(b->cap_stream, &g);
       if (e != hipSuccess) {
@@ -763,8 +796,8 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
       }
     }
     hipError_t e =
-        launch_iteration(b->k, b->async_mode, b->rescan, b->hub_shared, L, grid, mg, b->stream,
-                         eb, ee);
+        launch_iteration(b->k, b->async_mode, b->rescan, b->hub_shared, b->shared_vars, b->wide, L,
+                         grid, mg, b->stream, eb, ee);
     if (e != hipSuccess) return fail_hip_b(b, e, "iteration launch");
     if (b->check_every > 0 && (i + 1) % b->check_every == 0 && i + 1 < iters) {
       HIP_TRY_B(b, hipMemcpyAsync(b->h_finished, b->d_finished, sizeof(int32_t),
@@ -837,7 +870,7 @@ static int check_config(const lpa_config &cfg) {
   if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
   if ((cfg.flags &
        ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN | LPA_HUB_SHARED |
-         LPA_CAPTURE)) != 0)
+         LPA_CAPTURE | LPA_SHARED_VARS)) != 0)
     return LPA_ERR_UNSUPPORTED;
   if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
   return LPA_OK;
@@ -851,13 +884,15 @@ int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter, const lpa_c
     cfg = *cfg_in;
   else
     lpa_config_default(&cfg);
-  if (n < 0 || nnz < 0 || nnz >= (int64_t)INT32_MAX || max_iter < 0) return LPA_ERR_ARG;
+  if (n < 0 || nnz < 0 || nnz >= kMaxEntries || max_iter < 0) return LPA_ERR_ARG;
   int rc = check_config(cfg);
   if (rc) return rc;
   if ((rc = check_k(k, cfg.flags)) != LPA_OK) return rc;
   const bool async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   const int lane_max = cfg.lane_max_degree > 0 ? cfg.lane_max_degree : default_lane_max(async_mode);
-  *bytes = plan_layout(n, nnz, k, max_iter, async_mode, lane_max).total;
+  const Layout Ly = plan_layout(n, nnz, k, max_iter, async_mode, lane_max);
+  if (Ly.too_many_segs) return LPA_ERR_UNSUPPORTED;
+  *bytes = Ly.total;
   return LPA_OK;
 }
 
@@ -885,14 +920,17 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     lpa_config_default(&cfg);
   int rc = check_config(cfg);
   if (rc) return rc;
-  if (g->n < 0 || g->n == INT32_MAX || g->nnz < 0 || g->nnz >= (int64_t)INT32_MAX) return LPA_ERR_ARG;
-  if (g->n > 0 && !g->row_ptr) return LPA_ERR_ARG;
+  if (g->n < 0 || g->n == INT32_MAX || g->nnz < 0 || g->nnz >= kMaxEntries) return LPA_ERR_ARG;
+  if (g->row_ptr && g->row_ptr64) return LPA_ERR_ARG;
+  if (g->n > 0 && !g->row_ptr && !g->row_ptr64) return LPA_ERR_ARG;
+  if (!g->row_ptr64 && g->nnz >= (int64_t)INT32_MAX) return LPA_ERR_ARG;  // int32 offsets
   if (g->nnz > 0 && !g->col_idx) return LPA_ERR_ARG;
   if (g->n == 0 && g->nnz != 0) return LPA_ERR_ARG;
   if (!(tol >= 0.0 && tol <= 1.0) || max_iter < 0) return LPA_ERR_ARG;
   if ((rc = check_k(k, cfg.flags)) != LPA_OK) return rc;
   // graph arrays the kernels could not read are refused here, not faulted on
-  if (g->n > 0 && pointer_location(g->row_ptr) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
+  const void *rp_any = g->row_ptr64 ? (const void *)g->row_ptr64 : (const void *)g->row_ptr;
+  if (g->n > 0 && pointer_location(rp_any) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
   if (g->nnz > 0 && pointer_location(g->col_idx) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
   if (weights && g->nnz > 0 && pointer_location(weights) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
 
@@ -901,7 +939,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   h->stream = (hipStream_t)cfg.stream;
   h->n = g->n;
   h->nnz = g->nnz;
-  h->row_ptr = g->row_ptr;
+  h->row_ptr = RowPtr{g->row_ptr64 ? nullptr : g->row_ptr, g->row_ptr64};
   h->col = g->col_idx;
   h->w = weights;
   h->k = k;
@@ -922,6 +960,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   // one block for every array of the handle: the caller's workspace or ours
   const int n = h->n;
   const Layout Ly = plan_layout(n, h->nnz, k, max_iter, h->async_mode, h->lane_max);
+  if (Ly.too_many_segs) return bail(set_err(h, LPA_ERR_UNSUPPORTED, "too many hub segments"));
   if (cfg.workspace) {
     if (cfg.workspace_bytes < Ly.total || ((uintptr_t)cfg.workspace & 255) != 0)
       return bail(LPA_ERR_NOMEM);
@@ -1033,6 +1072,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   h->self->k = kernel_k(k, cfg.flags);
   h->self->rescan = (cfg.flags & LPA_RESCAN) != 0;
   h->self->hub_shared = (cfg.flags & LPA_HUB_SHARED) != 0;
+  h->self->shared_vars = (cfg.flags & LPA_SHARED_VARS) != 0;
   h->self->capture = (cfg.flags & LPA_CAPTURE) != 0;
   h->self->async_mode = h->async_mode;
   h->self->stream = h->stream;
@@ -1104,6 +1144,7 @@ int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **
   b->k = kernel_k(k, cfg.flags);
   b->rescan = (cfg.flags & LPA_RESCAN) != 0;
   b->hub_shared = (cfg.flags & LPA_HUB_SHARED) != 0;
+  b->shared_vars = (cfg.flags & LPA_SHARED_VARS) != 0;
   b->capture = (cfg.flags & LPA_CAPTURE) != 0;
   b->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   b->stream = (hipStream_t)cfg.stream;

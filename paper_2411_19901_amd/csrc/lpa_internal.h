@@ -37,6 +37,17 @@ __host__ __device__ inline int degree_class(int d, int lane_max) {
   return kHubClasses + kLaneBuckets + (kLaneExact - d);
 }
 
+// CSR row offsets, 32- or 64-bit: exactly one pointer is set for a graph
+// with vertices.  The choice is the same for every vertex of a graph, so
+// the test is a uniform branch.
+struct RowPtr {
+  const int32_t *p32;
+  const int64_t *p64;
+  __device__ __forceinline__ long long operator[](long long i) const {
+    return p64 ? (long long)p64[i] : (long long)p32[i];
+  }
+};
+
 // Device-resident progress of one graph, updated by the convergence kernel.
 struct GraphStatus {
   int32_t iter;       // iterations run so far
@@ -59,7 +70,7 @@ struct GraphDesc {
   int32_t rho;
   int32_t items;      // move-kernel work items per iteration
   double tol;
-  const int32_t *row_ptr;
+  RowPtr row_ptr;
   const int32_t *col;
   const float *w;     // nullable: unit weights
   int32_t *C[2];      // det: labels of even / odd iterations; async: both C[0]
@@ -98,7 +109,7 @@ struct Launch {
 // Per-graph view used by the move kernels for one iteration.
 struct MoveArgs {
   int32_t n;
-  const int32_t *row_ptr;
+  RowPtr row_ptr;
   const int32_t *col;
   const float *w;
   int32_t *C;              // labels read this iteration (async: read/write)
@@ -124,14 +135,17 @@ struct MoveArgs {
 // the double scan (LPA_RESCAN, k > 0 only); hub_shared replaces the hub
 // segments' partial sketches by one shared sketch per hub (LPA_HUB_SHARED,
 // async, k > 0, no double scan).
+// shared_vars: LPA_SHARED_VARS (det sketch rule, single scan).
+// wide: some graph of the launch has int64 row offsets (the kernels then
+// compute CSR positions in 64 bits).
 // Enqueue one iteration of every graph in the launch (async: hub flag
 // snapshot, k_move, hub merge, and for the double scan the hub re-weighting
 // and decision; det: k_move; then the convergence test).  Non-null events
 // are recorded around k_move only.
-hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared, const Launch &L,
-                            int grid, int merge_grid, hipStream_t s, hipEvent_t ev_beg,
-                            hipEvent_t ev_end);
-int move_blocks_per_cu(int k, bool async_mode, bool rescan);
+hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared,
+                            bool shared_vars, bool wide, const Launch &L, int grid,
+                            int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
+int move_blocks_per_cu(int k, bool async_mode, bool rescan, bool shared_vars, bool wide);
 
 // Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read
 // by one wavefront each, order[n_hubs, n_hubs + n_lane) one lane each.
@@ -141,7 +155,7 @@ struct ModArgs {
   const int32_t *order;
   int32_t n_hubs;
   int32_t n_lane;
-  const int32_t *row_ptr;
+  RowPtr row_ptr;
   const int32_t *col;
   const float *w;
   const int32_t *lab;

@@ -37,8 +37,8 @@ __device__ void add_by_label(double *tot, int c, double x, bool on) {
 // staging: adds matching weights to `in` and stages the weights for the
 // row owners' K_i sums.
 template <int TW, int T>
-__device__ __forceinline__ void mod_step(const ModArgs &m, Stage<T> &st, int lane, int t0, int tn,
-                                         double &ki, double &in) {
+__device__ __forceinline__ void mod_step(const ModArgs &m, Stage<T, long long> &st, int lane, int t0,
+                                         int tn, double &ki, double &in) {
 #pragma unroll
   for (int i = 0; i < TW; ++i) {
     const int slot = i * kWave + lane;
@@ -46,7 +46,7 @@ __device__ __forceinline__ void mod_step(const ModArgs &m, Stage<T> &st, int lan
     const int p = t0 + j;
     float x = 0.0f;
     if (p < st.len[r]) {
-      const int e = st.beg[r] + p;
+      const long long e = st.beg[r] + p;
       const int c = __builtin_nontemporal_load(m.col + e);
       x = m.w ? __builtin_nontemporal_load(m.w + e) : 1.0f;
       if (m.lab[c] == st.self[r]) in += (double)x;
@@ -64,13 +64,14 @@ __device__ __forceinline__ void mod_step(const ModArgs &m, Stage<T> &st, int lan
 
 // One lane per row: entries [beg, beg + len) of vertex v (v < 0: none).
 template <int T>
-__device__ void mod_lane_rows(const ModArgs &m, Stage<T> &st, int lane, int v, double &k_acc,
-                              double &in_acc) {
-  int beg = 0, len = 0, ci = -1;
+__device__ void mod_lane_rows(const ModArgs &m, Stage<T, long long> &st, int lane, int v,
+                              double &k_acc, double &in_acc) {
+  long long beg = 0;
+  int len = 0, ci = -1;
   if (v >= 0) {
     ci = m.lab[v];
     beg = m.row_ptr[v];
-    len = m.row_ptr[v + 1] - beg;
+    len = (int)(m.row_ptr[v + 1] - beg);
   }
   st.beg[lane] = beg;
   st.len[lane] = len;
@@ -103,15 +104,15 @@ __device__ void mod_hub(const ModArgs &m, int v, double &k_acc, double &in_acc, 
                         double &ps) {
   const int lane = threadIdx.x & (kWave - 1);
   const int ci = m.lab[v];
-  const int rb = m.row_ptr[v], re = m.row_ptr[v + 1];
+  const long long rb = m.row_ptr[v], re = m.row_ptr[v + 1];
   constexpr int U = 4;
   double ki = 0.0, in = 0.0;
-  for (int e0 = rb; e0 < re; e0 += U * kWave) {
+  for (long long e0 = rb; e0 < re; e0 += U * kWave) {
     int c[U];
     float x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * kWave + lane;
+      const long long e = e0 + u * kWave + lane;
       c[u] = -1;
       x[u] = 0.0f;
       if (e < re) {
@@ -140,7 +141,7 @@ __device__ void mod_hub(const ModArgs &m, int v, double &k_acc, double &in_acc, 
 }
 
 __global__ __launch_bounds__(kBlock) void k_modularity(ModArgs m) {
-  __shared__ Stage<kStageT> stage[kBlock / kWave];
+  __shared__ Stage<kStageT, long long> stage[kBlock / kWave];  // 64-bit row positions
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = rfl(threadIdx.x / kWave);
   const int wave = rfl(blockIdx.x * (kBlock / kWave) + wib);

@@ -38,8 +38,20 @@
 #include <limits.h>
 #include <math.h>
 
+#include <type_traits>
+
 namespace lpa {
 
+
+// Row offset v of a graph as position type Pos: int reads the int32 offsets
+// (graphs of fewer than 2^31 entries); long long reads either width.
+template <class Pos>
+__device__ __forceinline__ Pos row_at(const RowPtr &rp, int v) {
+  if constexpr (sizeof(Pos) == 8)
+    return rp[v];
+  else
+    return rp.p32[v];
+}
 
 // ---------------------------------------------------------------------------
 // Register sketch: one lane owns all K slots.
@@ -159,8 +171,8 @@ constexpr int slots_of(int K) { return K == 0 ? 1 : K; }
 // Load one staging step of TW entries for each of the 64 rows (TW <= T):
 // slot i * 64 + lane holds entry t0 + j of row r, (r, j) = (slot / TW,
 // slot % TW), stored at r * (TW + 1) + j.
-template <int TW, int T>
-__device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T> &st, int lane, int t0) {
+template <int TW, int T, class Pos>
+__device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T, Pos> &st, int lane, int t0) {
 #pragma unroll
   for (int i = 0; i < TW; ++i) {
     const int slot = i * kWave + lane;
@@ -169,7 +181,7 @@ __device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T> &st, int 
     int lab = -1;
     float x = 0.0f;
     if (p < st.len[r]) {
-      const int e = st.beg[r] + p;
+      const Pos e = st.beg[r] + p;
       const int c = __builtin_nontemporal_load(a.col + e);
       x = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
       if (c == st.self[r]) x = 0.0f;
@@ -186,8 +198,8 @@ __device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T> &st, int 
 // or T entries per row, the narrowest that covers what the wavefront's
 // longest row has left: with short rows a wide step would leave most load
 // slots idle.
-template <int T, class Feed>
-__device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T> &st, int lane, int beg,
+template <int T, class Pos, class Feed>
+__device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
                                             int len, int self, Feed &&feed) {
   st.beg[lane] = beg;
   st.len[lane] = len;
@@ -216,8 +228,8 @@ __device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T> &st, int
 
 // Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
 // nothing).  All lanes of the wavefront must call it together.
-template <class SK, int T>
-__device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T> &st, int lane, int beg,
+template <class SK, int T, class Pos>
+__device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
                                             int len, int self, SK &S) {
   staged_rows<T>(a, st, lane, beg, len, self, [&](int lab, float x) { S.add(lab, x); });
 }
@@ -261,8 +273,9 @@ __device__ __forceinline__ void mark(const MoveArgs &a, int j) { a.act_next[j] =
 
 // Mark the neighbours of every lane whose `moved` is set (entries [beg, beg +
 // len) of its row), with row-contiguous column loads by the whole wavefront.
-template <int TW, int T>
-__device__ __forceinline__ void mark_step(const MoveArgs &a, const Stage<T> &st, int lane, int t0) {
+template <int TW, int T, class Pos>
+__device__ __forceinline__ void mark_step(const MoveArgs &a, const Stage<T, Pos> &st, int lane,
+                                          int t0) {
 #pragma unroll
   for (int i = 0; i < TW; ++i) {
     const int slot = i * kWave + lane;
@@ -275,8 +288,8 @@ __device__ __forceinline__ void mark_step(const MoveArgs &a, const Stage<T> &st,
 // Mark the neighbours of every lane whose `moved` is set (entries [beg, beg +
 // len) of its row), with row-contiguous column loads by the whole wavefront
 // and the same step widths as staged_rows.
-template <int T>
-__device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T> &st, int lane, int beg,
+template <int T, class Pos>
+__device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
                                             int len, bool moved) {
   if (__ballot(moved) == 0ull) return;
   st.beg[lane] = beg;
@@ -314,11 +327,12 @@ struct HubChunks {
   int lab[D];
   float x[D];  // 0 for padding and self-loops
 
-  __device__ __forceinline__ void load(const MoveArgs &a, int v, int sb, int end, int lane) {
+  template <class Pos>
+  __device__ __forceinline__ void load(const MoveArgs &a, int v, Pos sb, Pos end, int lane) {
     int c[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const int e = sb + d * kWave + lane;
+      const Pos e = sb + d * kWave + lane;
       c[d] = -1;
       x[d] = 0.0f;
       if (e < end) {
@@ -333,22 +347,22 @@ struct HubChunks {
 
 // Call consume(lab, x, cnt) for every 64-entry chunk of [beg, end) in order
 // (cnt = entries of the chunk; lanes >= cnt hold padding).
-template <class Consume>
-__device__ __forceinline__ void hub_feed(const MoveArgs &a, int v, int beg, int end, int lane,
+template <class Pos, class Consume>
+__device__ __forceinline__ void hub_feed(const MoveArgs &a, int v, Pos beg, Pos end, int lane,
                                          Consume &&consume) {
   // The chain of one hub bounds the whole iteration while the other
   // wavefronts of its SIMD stream short rows: let it issue first.
   __builtin_amdgcn_s_setprio(3);
   HubChunks<kHubDepth> cur, nxt;
   cur.load(a, v, beg, end, lane);
-  for (int sb = beg; sb < end; sb += kHubDepth * kWave) {
-    const int nb = sb + kHubDepth * kWave;
+  for (Pos sb = beg; sb < end; sb += kHubDepth * kWave) {
+    const Pos nb = sb + kHubDepth * kWave;
     if (nb < end) nxt.load(a, v, nb, end, lane);
 #pragma unroll 1
     for (int d = 0; d < kHubDepth; ++d) {
-      const int base = sb + d * kWave;
+      const Pos base = sb + d * kWave;
       if (base >= end) break;
-      consume(cur.lab[0], cur.x[0], min(kWave, end - base));
+      consume(cur.lab[0], cur.x[0], (int)min((Pos)kWave, (Pos)(end - base)));
 #pragma unroll
       for (int q = 0; q + 1 < kHubDepth; ++q) {
         cur.lab[q] = cur.lab[q + 1];
@@ -367,7 +381,7 @@ __device__ __forceinline__ void hub_feed(const MoveArgs &a, int v, int beg, int 
 // scalar lane indices and no cross-lane votes; the first entry without a
 // key takes the full sketch step, after which only the lanes whose label
 // was the replaced key or is the new key change their slot.
-template <int K, bool RS>
+template <int K, bool RS, class Pos>
 __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &scanned,
                                unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -377,7 +391,7 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
     return;
   }
   if (lane == 0) a.act_cur[v] = 0;
-  const int beg = rfl(a.row_ptr[v]), end = rfl(a.row_ptr[v + 1]);
+  const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
   int key = -1;
   float val = 0.0f;
   hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
@@ -460,7 +474,96 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
   if (lane == 0) a.Cn[v] = moved ? c : cv;
   if (moved) {
     changed += 1;
-    for (int q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
+    for (Pos q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
+  }
+  scanned += (unsigned long long)(end - beg);
+}
+
+// LPA_SHARED_VARS: the same slot-per-lane sketch and CSR order as
+// hub_vertex_det, with the lanes communicating through shared variables in
+// LDS instead of wavefront votes (the shared-variable protocol of Algorithm
+// 5 and Section 4.1): per entry, the lane whose slot holds the label
+// announces its slot index; if none does, the lanes of empty slots take the
+// lowest index with an LDS atomic minimum; if none is empty, the smallest
+// slot value is found the same way (non-negative floats order like their
+// bit patterns) and every slot is decremented.  Same results as
+// hub_vertex_det; one entry at a time, with LDS round trips instead of
+// register votes.
+template <int K, class Pos>
+__device__ void hub_vertex_det_sv(const MoveArgs &a, int v, unsigned long long &scanned,
+                                  unsigned long long &changed) {
+  __shared__ int sv[kBlock / kWave][2];  // per wavefront: [0] slot index, [1] minimum (bits)
+  const int lane = threadIdx.x & (kWave - 1);
+  int *has = sv[threadIdx.x / kWave];
+  const int cv = a.C[v];
+  if (a.act_cur[v] == 0) {
+    if (lane == 0) a.Cn[v] = cv;
+    return;
+  }
+  if (lane == 0) a.act_cur[v] = 0;
+  const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
+  int key = -1;
+  float val = 0.0f;
+  auto first_free = [&]() {  // lowest empty slot, K if none
+    if (lane == 0) has[0] = K;
+    wave_lds_sync();
+    if (lane < K && val == 0.0f) atomicMin(&has[0], lane);
+    wave_lds_sync();
+    const int s = rfl(has[0]);
+    wave_lds_sync();
+    return s;
+  };
+  hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
+    for (int t = 0; t < cnt; ++t) {
+      const int c = rl(lab, t);
+      const float w = rl_f(x, t);
+      if (!(w > 0.0f)) continue;  // zero weight: no-op (self-loops, padding)
+      if (lane == 0) has[0] = -1;
+      wave_lds_sync();
+      if (lane < K && key == c) has[0] = lane;  // keys are unique: one writer at most
+      wave_lds_sync();
+      const int hs = rfl(has[0]);
+      wave_lds_sync();
+      if (hs >= 0) {
+        if (lane == hs) val += w;
+        continue;
+      }
+      float r = w;
+      int s = first_free();
+      if (s == K) {  // every slot live: decrement by d = min(w, smallest slot)
+        if (lane == 0) has[1] = __float_as_int(w);
+        wave_lds_sync();
+        if (lane < K) atomicMin(&has[1], __float_as_int(val));
+        wave_lds_sync();
+        const float m = __int_as_float(rfl(has[1]));
+        wave_lds_sync();
+        if (lane < K) val = val - m;
+        r = w - m;
+        s = r > 0.0f ? first_free() : K;
+      }
+      if (lane == s) {  // the (residue of the) pair takes the free slot
+        key = c;
+        val = r;
+      }
+    }
+  });
+  // heaviest live slot, ties to the lowest label; keep when empty
+  int bk = cv;
+  float bv = 0.0f;
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const float vs = rl_f(val, s);
+    const int ks = rl(key, s);
+    if (vs > bv || (vs == bv && vs > 0.0f && ks < bk)) {
+      bk = ks;
+      bv = vs;
+    }
+  }
+  const bool moved = bk != cv && (!a.pickless || bk < cv);
+  if (lane == 0) a.Cn[v] = moved ? bk : cv;
+  if (moved) {
+    changed += 1;
+    for (Pos q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
   }
   scanned += (unsigned long long)(end - beg);
 }
@@ -468,6 +571,7 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
 // LPA_MODE_DET hub path for the vote of Algorithm 3: the vote consumes each
 // chunk in CSR order through lane reads (every lane holds the same
 // candidate).
+template <class Pos>
 __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &scanned,
                                   unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -477,7 +581,7 @@ __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &
     return;
   }
   if (lane == 0) a.act_cur[v] = 0;
-  const int beg = rfl(a.row_ptr[v]), end = rfl(a.row_ptr[v + 1]);
+  const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
   BmSketch S;
   S.clear();
   hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
@@ -488,7 +592,7 @@ __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &
   if (lane == 0) a.Cn[v] = moved ? c : cv;
   if (moved) {
     changed += 1;
-    for (int q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
+    for (Pos q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
   }
   scanned += (unsigned long long)(end - beg);
 }
@@ -498,21 +602,22 @@ __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &
 // hub h = seg_hub[u] (async only); otherwise whole vertex order[n_hubs + u -
 // n_seg].
 // ---------------------------------------------------------------------------
-template <int K, bool ASYNC, bool RS>
-__device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st, int u,
+template <int K, bool ASYNC, bool RS, class Pos>
+__device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos> &st, int u,
                                            unsigned long long &scanned,
                                            unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
-  int v = -1, beg = 0, len = 0, cv = 0, pslot = -1;
+  int v = -1, len = 0, cv = 0, pslot = -1;
+  Pos beg = 0;
   bool whole = false, active = false;
   if (ASYNC && u < a.n_seg) {
     const int h = a.seg_hub[u];
     v = a.order[h];
     active = a.hub_act[h] != 0;
     const int q = u - a.hub_pbase[h];
-    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
-    beg = rb + q * a.seg_len;
-    len = min(a.seg_len, re - beg);
+    const Pos rb = row_at<Pos>(a.row_ptr, v), re = row_at<Pos>(a.row_ptr, v + 1);
+    beg = rb + (Pos)q * a.seg_len;
+    len = (int)min((Pos)a.seg_len, (Pos)(re - beg));
     pslot = u;
   } else if (u < a.n_seg + a.n_lane) {
     v = a.order[a.n_hubs + (u - a.n_seg)];
@@ -521,8 +626,8 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT> &st
     cv = a.C[v];
     if (active) {
       a.act_cur[v] = 0;
-      beg = a.row_ptr[v];
-      len = a.row_ptr[v + 1] - beg;
+      beg = row_at<Pos>(a.row_ptr, v);
+      len = (int)(row_at<Pos>(a.row_ptr, v + 1) - beg);
     }
   }
   if (!active) len = 0;
@@ -622,9 +727,9 @@ __device__ __forceinline__ void flush_counts(unsigned long long *dN, unsigned lo
   scanned_lane = scanned_w = changed_w = 0;
 }
 
-template <int K, bool ASYNC, bool RS>
+template <int K, bool ASYNC, bool RS, class Pos, bool SV = false>
 __device__ __forceinline__ void move_body(const Launch &L) {
-  __shared__ Stage<kStageT> stage[kBlock / kWave];
+  __shared__ Stage<kStageT, Pos> stage[kBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int wib = rfl(threadIdx.x / kWave);
   const int wave = rfl(blockIdx.x * (kBlock / kWave) + wib);
@@ -648,26 +753,41 @@ __device__ __forceinline__ void move_body(const Launch &L) {
     const int hub_items = ASYNC ? 0 : a.n_hubs;
     if (local < hub_items) {
       if constexpr (K == 0)
-        hub_vertex_det_bm(a, a.order[local], scanned_w, changed_w);
+        hub_vertex_det_bm<Pos>(a, a.order[local], scanned_w, changed_w);
+      else if constexpr (SV)
+        hub_vertex_det_sv<K, Pos>(a, a.order[local], scanned_w, changed_w);
       else
-        hub_vertex_det<K, RS>(a, a.order[local], scanned_w, changed_w);
+        hub_vertex_det<K, RS, Pos>(a, a.order[local], scanned_w, changed_w);
     } else
-      lane_units<K, ASYNC, RS>(a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane,
+      lane_units<K, ASYNC, RS, Pos>(a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane,
                                changed_w);
   }
   flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
 }
 
+// CSR positions are int for graphs of fewer than 2^31 entries (W = false),
+// long long otherwise (W = true, which also reads int32 offsets): 32-bit
+// positions keep one register per staged load address.
+template <bool W>
+using PosOf = typename std::conditional<W, long long, int>::type;
+
 // One iteration's label moves (single scan) ...
-template <int K, bool ASYNC>
+template <int K, bool ASYNC, bool W>
 __global__ __launch_bounds__(kBlock) void k_move(Launch L) {
-  move_body<K, ASYNC, false>(L);
+  move_body<K, ASYNC, false, PosOf<W>>(L);
 }
 
 // ... and with the double scan (LPA_RESCAN; sketch rule only).
-template <int K, bool ASYNC>
+template <int K, bool ASYNC, bool W>
 __global__ __launch_bounds__(kBlock) void k_move_rescan(Launch L) {
-  move_body<K, ASYNC, true>(L);
+  move_body<K, ASYNC, true, PosOf<W>>(L);
+}
+
+// ... and with shared variables instead of votes in the hub path
+// (LPA_SHARED_VARS; LPA_MODE_DET, sketch rule, single scan).
+template <int K, bool W>
+__global__ __launch_bounds__(kBlock) void k_move_sv(Launch L) {
+  move_body<K, false, false, PosOf<W>, true>(L);
 }
 
 // ---------------------------------------------------------------------------
@@ -879,8 +999,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
     if (a.hub_act[h] == 0) continue;
     const int v = a.order[h];
     const int q = u - a.hub_pbase[h];
-    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
-    const int beg = rb + q * a.seg_len, end = min(beg + a.seg_len, re);
+    const long long rb = a.row_ptr[v], re = a.row_ptr[v + 1];
+    const long long beg = rb + (long long)q * a.seg_len, end = min(beg + a.seg_len, re);
     int cand[K];
     float acc[K];
 #pragma unroll
@@ -889,12 +1009,12 @@ __global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
       acc[s] = 0.0f;
     }
     constexpr int U = 4;
-    for (int e0 = beg; e0 < end; e0 += U * kWave) {
+    for (long long e0 = beg; e0 < end; e0 += U * kWave) {
       int lab[U];
       float x[U];
 #pragma unroll
       for (int t = 0; t < U; ++t) {
-        const int e = e0 + t * kWave + lane;
+        const long long e = e0 + t * kWave + lane;
         lab[t] = -1;
         x[t] = 0.0f;
         if (e < end) {
@@ -1016,9 +1136,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_mark(Launch L) {
     if (a.hub_act[h] == 0) continue;
     const int v = a.order[h];
     const int q = u - a.hub_pbase[h];
-    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
-    const int beg = rb + q * a.seg_len, end = min(beg + a.seg_len, re);
-    for (int e = beg + lane; e < end; e += kWave) mark(a, __builtin_nontemporal_load(a.col + e));
+    const long long rb = a.row_ptr[v], re = a.row_ptr[v + 1];
+    const long long beg = rb + (long long)q * a.seg_len, end = min(beg + a.seg_len, re);
+    for (long long e = beg + lane; e < end; e += kWave)
+      mark(a, __builtin_nontemporal_load(a.col + e));
   }
 }
 
@@ -1083,8 +1204,8 @@ __global__ __launch_bounds__(256) void k_hub_shared(Launch L) {
       val[threadIdx.x] = 0.0f;
     }
     __syncthreads();
-    const int rb = a.row_ptr[v], re = a.row_ptr[v + 1];
-    for (int e = rb + (int)threadIdx.x; e < re; e += blockDim.x) {
+    const long long rb = a.row_ptr[v], re = a.row_ptr[v + 1];
+    for (long long e = rb + threadIdx.x; e < re; e += blockDim.x) {
       const int j = __builtin_nontemporal_load(a.col + e);
       if (j == v) continue;
       const float w = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
@@ -1136,7 +1257,7 @@ __global__ void k_finish(Launch L) {
 }
 
 // ---------------------------------------------------------------------------
-template <int K, bool ASYNC, bool RS, bool HS = false>
+template <int K, bool ASYNC, bool RS, bool W, bool HS = false, bool SV = false>
 static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_t s,
                            hipEvent_t ev_beg, hipEvent_t ev_end) {
   hipError_t e = hipSuccess;
@@ -1147,9 +1268,11 @@ static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_
   if (ev_beg && (e = hipEventRecord(ev_beg, s)) != hipSuccess) return e;
   if (L.total_items > 0) {
     if constexpr (RS)
-      hipLaunchKernelGGL((k_move_rescan<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, L);
+      hipLaunchKernelGGL((k_move_rescan<K, ASYNC, W>), dim3(grid), dim3(kBlock), 0, s, L);
+    else if constexpr (SV)
+      hipLaunchKernelGGL((k_move_sv<K, W>), dim3(grid), dim3(kBlock), 0, s, L);
     else
-      hipLaunchKernelGGL((k_move<K, ASYNC>), dim3(grid), dim3(kBlock), 0, s, L);
+      hipLaunchKernelGGL((k_move<K, ASYNC, W>), dim3(grid), dim3(kBlock), 0, s, L);
   }
   if (ev_end && (e = hipEventRecord(ev_end, s)) != hipSuccess) return e;
   if constexpr (HS) {  // shared hub sketches replace segments and merging
@@ -1174,82 +1297,132 @@ static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_
   return hipGetLastError();
 }
 
-template <int K, bool ASYNC, bool RS>
+template <int K, bool ASYNC, bool RS, bool W, bool SV = false>
 static int occ_t() {
   int nb = 0;
   const void *f;
   if constexpr (RS)
-    f = (const void *)k_move_rescan<K, ASYNC>;
+    f = (const void *)k_move_rescan<K, ASYNC, W>;
+  else if constexpr (SV)
+    f = (const void *)k_move_sv<K, W>;
   else
-    f = (const void *)k_move<K, ASYNC>;
+    f = (const void *)k_move<K, ASYNC, W>;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
-template <bool ASYNC, bool RS>
+template <bool ASYNC, bool RS, bool W>
 static hipError_t launch_mode(int k, const Launch &L, int grid, int merge_grid, hipStream_t s,
                               hipEvent_t b, hipEvent_t e) {
   switch (k) {
-    case 1: return launch_t<1, ASYNC, RS>(L, grid, merge_grid, s, b, e);
-    case 2: return launch_t<2, ASYNC, RS>(L, grid, merge_grid, s, b, e);
-    case 4: return launch_t<4, ASYNC, RS>(L, grid, merge_grid, s, b, e);
-    case 8: return launch_t<8, ASYNC, RS>(L, grid, merge_grid, s, b, e);
-    case 16: return launch_t<16, ASYNC, RS>(L, grid, merge_grid, s, b, e);
-    case 32: return launch_t<32, ASYNC, RS>(L, grid, merge_grid, s, b, e);
+    case 1: return launch_t<1, ASYNC, RS, W>(L, grid, merge_grid, s, b, e);
+    case 2: return launch_t<2, ASYNC, RS, W>(L, grid, merge_grid, s, b, e);
+    case 4: return launch_t<4, ASYNC, RS, W>(L, grid, merge_grid, s, b, e);
+    case 8: return launch_t<8, ASYNC, RS, W>(L, grid, merge_grid, s, b, e);
+    case 16: return launch_t<16, ASYNC, RS, W>(L, grid, merge_grid, s, b, e);
+    case 32: return launch_t<32, ASYNC, RS, W>(L, grid, merge_grid, s, b, e);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <bool ASYNC, bool RS>
+template <bool ASYNC, bool RS, bool W>
 static int occ_mode(int k) {
   switch (k) {
-    case 1: return occ_t<1, ASYNC, RS>();
-    case 2: return occ_t<2, ASYNC, RS>();
-    case 4: return occ_t<4, ASYNC, RS>();
-    case 8: return occ_t<8, ASYNC, RS>();
-    case 16: return occ_t<16, ASYNC, RS>();
-    case 32: return occ_t<32, ASYNC, RS>();
+    case 1: return occ_t<1, ASYNC, RS, W>();
+    case 2: return occ_t<2, ASYNC, RS, W>();
+    case 4: return occ_t<4, ASYNC, RS, W>();
+    case 8: return occ_t<8, ASYNC, RS, W>();
+    case 16: return occ_t<16, ASYNC, RS, W>();
+    case 32: return occ_t<32, ASYNC, RS, W>();
     default: return 1;
   }
 }
 
-template <bool HS>
+template <bool HS, bool W>
 static hipError_t launch_hs(int k, const Launch &L, int grid, int merge_grid, hipStream_t s,
                             hipEvent_t b, hipEvent_t e) {
   switch (k) {
-    case 1: return launch_t<1, true, false, HS>(L, grid, merge_grid, s, b, e);
-    case 2: return launch_t<2, true, false, HS>(L, grid, merge_grid, s, b, e);
-    case 4: return launch_t<4, true, false, HS>(L, grid, merge_grid, s, b, e);
-    case 8: return launch_t<8, true, false, HS>(L, grid, merge_grid, s, b, e);
-    case 16: return launch_t<16, true, false, HS>(L, grid, merge_grid, s, b, e);
-    case 32: return launch_t<32, true, false, HS>(L, grid, merge_grid, s, b, e);
+    case 1: return launch_t<1, true, false, W, HS>(L, grid, merge_grid, s, b, e);
+    case 2: return launch_t<2, true, false, W, HS>(L, grid, merge_grid, s, b, e);
+    case 4: return launch_t<4, true, false, W, HS>(L, grid, merge_grid, s, b, e);
+    case 8: return launch_t<8, true, false, W, HS>(L, grid, merge_grid, s, b, e);
+    case 16: return launch_t<16, true, false, W, HS>(L, grid, merge_grid, s, b, e);
+    case 32: return launch_t<32, true, false, W, HS>(L, grid, merge_grid, s, b, e);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared, const Launch &L,
-                            int grid, int merge_grid, hipStream_t s, hipEvent_t ev_beg,
-                            hipEvent_t ev_end) {
+template <bool W>
+static hipError_t launch_sv(int k, const Launch &L, int grid, int merge_grid, hipStream_t s,
+                            hipEvent_t b, hipEvent_t e) {
+  switch (k) {
+    case 1: return launch_t<1, false, false, W, false, true>(L, grid, merge_grid, s, b, e);
+    case 2: return launch_t<2, false, false, W, false, true>(L, grid, merge_grid, s, b, e);
+    case 4: return launch_t<4, false, false, W, false, true>(L, grid, merge_grid, s, b, e);
+    case 8: return launch_t<8, false, false, W, false, true>(L, grid, merge_grid, s, b, e);
+    case 16: return launch_t<16, false, false, W, false, true>(L, grid, merge_grid, s, b, e);
+    case 32: return launch_t<32, false, false, W, false, true>(L, grid, merge_grid, s, b, e);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <bool W>
+static int occ_sv(int k) {
+  switch (k) {
+    case 1: return occ_t<1, false, false, W, true>();
+    case 2: return occ_t<2, false, false, W, true>();
+    case 4: return occ_t<4, false, false, W, true>();
+    case 8: return occ_t<8, false, false, W, true>();
+    case 16: return occ_t<16, false, false, W, true>();
+    case 32: return occ_t<32, false, false, W, true>();
+    default: return 1;
+  }
+}
+
+template <bool W>
+static hipError_t launch_iteration_w(int k, bool async_mode, bool rescan, bool hub_shared,
+                                     bool shared_vars, const Launch &L, int grid, int merge_grid,
+                                     hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
+  if (shared_vars) {  // det sketch rule without double scan only
+    if (async_mode || rescan || hub_shared || k == 0) return hipErrorInvalidValue;
+    return launch_sv<W>(k, L, grid, merge_grid, s, ev_beg, ev_end);
+  }
   if (hub_shared) {  // async sketch rule without double scan only
     if (!async_mode || rescan || k == 0) return hipErrorInvalidValue;
-    return launch_hs<true>(k, L, grid, merge_grid, s, ev_beg, ev_end);
+    return launch_hs<true, W>(k, L, grid, merge_grid, s, ev_beg, ev_end);
   }
   if (k == 0) {  // the vote of Algorithm 3 (no double scan)
     if (rescan) return hipErrorInvalidValue;
-    return async_mode ? launch_t<0, true, false>(L, grid, merge_grid, s, ev_beg, ev_end)
-                      : launch_t<0, false, false>(L, grid, merge_grid, s, ev_beg, ev_end);
+    return async_mode ? launch_t<0, true, false, W>(L, grid, merge_grid, s, ev_beg, ev_end)
+                      : launch_t<0, false, false, W>(L, grid, merge_grid, s, ev_beg, ev_end);
   }
   if (rescan)
-    return async_mode ? launch_mode<true, true>(k, L, grid, merge_grid, s, ev_beg, ev_end)
-                      : launch_mode<false, true>(k, L, grid, merge_grid, s, ev_beg, ev_end);
-  return async_mode ? launch_mode<true, false>(k, L, grid, merge_grid, s, ev_beg, ev_end)
-                    : launch_mode<false, false>(k, L, grid, merge_grid, s, ev_beg, ev_end);
+    return async_mode ? launch_mode<true, true, W>(k, L, grid, merge_grid, s, ev_beg, ev_end)
+                      : launch_mode<false, true, W>(k, L, grid, merge_grid, s, ev_beg, ev_end);
+  return async_mode ? launch_mode<true, false, W>(k, L, grid, merge_grid, s, ev_beg, ev_end)
+                    : launch_mode<false, false, W>(k, L, grid, merge_grid, s, ev_beg, ev_end);
 }
 
-int move_blocks_per_cu(int k, bool async_mode, bool rescan) {
-  if (k == 0) return async_mode ? occ_t<0, true, false>() : occ_t<0, false, false>();
-  if (rescan) return async_mode ? occ_mode<true, true>(k) : occ_mode<false, true>(k);
-  return async_mode ? occ_mode<true, false>(k) : occ_mode<false, false>(k);
+hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared,
+                            bool shared_vars, bool wide, const Launch &L, int grid,
+                            int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end) {
+  return wide ? launch_iteration_w<true>(k, async_mode, rescan, hub_shared, shared_vars, L, grid,
+                                         merge_grid, s, ev_beg, ev_end)
+              : launch_iteration_w<false>(k, async_mode, rescan, hub_shared, shared_vars, L, grid,
+                                          merge_grid, s, ev_beg, ev_end);
+}
+
+template <bool W>
+static int move_blocks_w(int k, bool async_mode, bool rescan, bool shared_vars) {
+  if (shared_vars && k > 0 && !async_mode && !rescan) return occ_sv<W>(k);
+  if (k == 0) return async_mode ? occ_t<0, true, false, W>() : occ_t<0, false, false, W>();
+  if (rescan) return async_mode ? occ_mode<true, true, W>(k) : occ_mode<false, true, W>(k);
+  return async_mode ? occ_mode<true, false, W>(k) : occ_mode<false, false, W>(k);
+}
+
+int move_blocks_per_cu(int k, bool async_mode, bool rescan, bool shared_vars, bool wide) {
+  return wide ? move_blocks_w<true>(k, async_mode, rescan, shared_vars)
+              : move_blocks_w<false>(k, async_mode, rescan, shared_vars);
 }
 
 }  // namespace lpa

@@ -9,6 +9,20 @@
 namespace lpa {
 
 __device__ __forceinline__ int rfl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long rfl64(long long x) {
+  const unsigned long long u = (unsigned long long)x;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+// readfirstlane of an int or a long long
+template <class T>
+__device__ __forceinline__ T rfl_as(T x) {
+  if constexpr (sizeof(T) == 8)
+    return rfl64(x);
+  else
+    return rfl(x);
+}
 __device__ __forceinline__ float rfl_f(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
@@ -41,9 +55,9 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 // (slot / T, slot % T), so its loads are row-contiguous; each lane then
 // reads its own row back.  Rows are padded to T + 1 words against bank
 // conflicts.
-template <int T>
+template <int T, class P = int>
 struct Stage {
-  int beg[kWave];
+  P beg[kWave];  // CSR position of each row's first entry (P: offset type)
   int len[kWave];
   int self[kWave];
   int lab[kWave * (T + 1)];

@@ -236,3 +236,90 @@ def batch_graph(spec: BatchSpec, seed: int, index: int,
 
 def batch(count: int = 512, seed: int = 512, **kw) -> List[Graph]:
     return [batch_graph(s, seed, i) for i, s in enumerate(batch_specs(count, seed, **kw))]
+
+
+# ------------------------------------------------------------------ ring + hubs
+# A graph of closed form, so that one far beyond 2^31 CSR entries can be
+# built directly in device memory and any of its rows recomputed on the host:
+#   * lane vertices j = 0 .. L-1: neighbours (j + o) mod L for o = -r .. -1,
+#     1 .. r (in that order), then the hub L + (j mod H);
+#   * hubs L + t, t = 0 .. H-1: neighbours t, t + H, t + 2H, ... < L;
+#   * weight of edge {i, j}: a hash of (min, max, seed), an exact multiple of
+#     2^-24 in (0, 1], so both directions carry the same weight.
+# nnz = L (2r + 2); vertex ids and offsets are int64 in every formula.
+
+def _ring_weight(lo, hi, seed: int, xp):
+    x = lo * 0x9E3779 + hi * 0x85EBCA + (seed & 0xFFFFFF) * 0x27D4EB
+    x = x ^ (x >> 15)
+    x = (x & 0xFFFFFF) * 0xC2B2AE
+    x = x ^ (x >> 16)
+    u = (x & 0xFFFFFF) + 1
+    return u.astype(xp.float32) * np.float32(2.0 ** -24) if xp is np else \
+        u.to(xp.float32) * (2.0 ** -24)
+
+
+def ring_hubs_offsets(L: int, H: int, r: int) -> np.ndarray:
+    """int64 row offsets [n + 1] of the ring + hubs graph (n = L + H)."""
+    if not (0 < H <= L and L > 2 * r + 1 and r >= 1):
+        raise ValueError("need 0 < H <= L and L > 2r + 1")
+    rp = np.zeros(L + H + 1, np.int64)
+    rp[1:L + 1] = np.arange(1, L + 1, dtype=np.int64) * (2 * r + 1)
+    t = np.arange(H, dtype=np.int64)
+    hub_deg = (L - t + H - 1) // H
+    rp[L + 1:] = rp[L] + np.cumsum(hub_deg)
+    return rp
+
+
+def ring_hubs_rows(L: int, H: int, r: int, seed: int, vertices):
+    """Rows of the given vertices as a compact CSR (row_ptr int64 over the
+    list, col int32, w float32), recomputed from the closed form."""
+    vs = np.asarray(vertices, np.int64)
+    offs = np.concatenate([np.arange(-r, 0), np.arange(1, r + 1)]).astype(np.int64)
+    cols, ws, lens = [], [], []
+    for v in vs:
+        if v < L:
+            c = np.concatenate([(v + offs) % L, [L + v % H]]).astype(np.int64)
+        else:
+            c = np.arange(v - L, L, H, dtype=np.int64)
+        lo, hi = np.minimum(c, v), np.maximum(c, v)
+        cols.append(c.astype(np.int32))
+        ws.append(_ring_weight(lo, hi, seed, np))
+        lens.append(len(c))
+    rp = np.zeros(len(vs) + 1, np.int64)
+    rp[1:] = np.cumsum(lens)
+    col = np.concatenate(cols) if cols else np.zeros(0, np.int32)
+    w = np.concatenate(ws) if ws else np.zeros(0, np.float32)
+    return rp, col, w
+
+
+def ring_hubs_device(L: int, H: int, r: int, seed: int, device, chunk: int = 1 << 22):
+    """The whole ring + hubs graph built with torch on `device`:
+    (row_ptr int64 [n + 1], col int32 [nnz], w float32 [nnz])."""
+    import torch
+
+    rp_np = ring_hubs_offsets(L, H, r)
+    nnz = int(rp_np[-1])
+    rp = torch.from_numpy(rp_np).to(device)
+    col = torch.empty(nnz, dtype=torch.int32, device=device)
+    w = torch.empty(nnz, dtype=torch.float32, device=device)
+    D = 2 * r + 1
+    offs = torch.cat([torch.arange(-r, 0), torch.arange(1, r + 1)]).to(device=device,
+                                                                        dtype=torch.int64)
+    for j0 in range(0, L, chunk):
+        j1 = min(L, j0 + chunk)
+        j = torch.arange(j0, j1, dtype=torch.int64, device=device)
+        c = torch.empty((j1 - j0, D), dtype=torch.int64, device=device)
+        c[:, :2 * r] = torch.remainder(j[:, None] + offs[None, :], L)
+        c[:, 2 * r] = L + torch.remainder(j, H)
+        jj = j[:, None].expand(-1, D)
+        x = _ring_weight(torch.minimum(c, jj), torch.maximum(c, jj), seed, torch)
+        col[j0 * D:j1 * D] = c.reshape(-1).to(torch.int32)
+        w[j0 * D:j1 * D] = x.reshape(-1)
+        del c, jj, x
+    for t in range(H):
+        b, e = int(rp_np[L + t]), int(rp_np[L + t + 1])
+        c = torch.arange(t, L, H, dtype=torch.int64, device=device)
+        hub = torch.full_like(c, L + t)
+        col[b:e] = c.to(torch.int32)
+        w[b:e] = _ring_weight(c, hub, seed, torch)
+    return rp, col, w

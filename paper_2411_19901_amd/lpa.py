@@ -36,6 +36,7 @@ LPA_RULE_BM_PAPER = 0x200
 LPA_RESCAN = 0x400
 LPA_HUB_SHARED = 0x800
 LPA_CAPTURE = 0x1000
+LPA_SHARED_VARS = 0x2000
 
 MODES = {"det": LPA_MODE_DET, "async": LPA_MODE_ASYNC}
 # per-vertex rule: the k-slot weighted Misra-Gries sketch, or the
@@ -45,7 +46,8 @@ RULES = {"mg": 0, "bm_paper": LPA_RULE_BM_PAPER}
 
 class LpaGraph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
-                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("row_ptr64", ctypes.c_void_p)]
 
 
 class LpaConfig(ctypes.Structure):
@@ -160,8 +162,11 @@ def lpa_config_default() -> LpaConfig:
 
 
 def lpa_init(n: int, nnz: int, row_ptr_ptr: int, col_ptr: int, weights_ptr: Optional[int],
-             k: int, tol: float, max_iter: int, seed: int, cfg: LpaConfig):
-    g = LpaGraph(n, nnz, row_ptr_ptr, col_ptr)
+             k: int, tol: float, max_iter: int, seed: int, cfg: LpaConfig,
+             offsets64: bool = False):
+    """``offsets64``: ``row_ptr_ptr`` points to int64 offsets (row_ptr64)."""
+    g = (LpaGraph(n, nnz, None, col_ptr, row_ptr_ptr) if offsets64
+         else LpaGraph(n, nnz, row_ptr_ptr, col_ptr))
     h = ctypes.c_void_p()
     rc = load().lpa_init(ctypes.byref(g), weights_ptr or None, k, tol, max_iter, seed,
                          ctypes.byref(cfg), ctypes.byref(h))
@@ -301,23 +306,26 @@ def lpa_batch_free(b) -> None:
 class LPA:
     """One label-propagation problem on device-resident torch tensors.
 
-    ``row_ptr`` / ``col`` are int32 CUDA tensors (symmetric CSR), ``weights``
-    a float32 CUDA tensor or None (unit weights).  The tensors are kept
-    alive by this object, as the library borrows them."""
+    ``row_ptr`` (int32, or int64 for graphs of 2^31 or more entries) and
+    ``col`` (int32) are CUDA tensors holding a symmetric CSR, ``weights`` a
+    float32 CUDA tensor or None (unit weights); pinned host tensors are
+    accepted too.  The tensors are kept alive by this object, as the
+    library borrows them."""
 
     def __init__(self, row_ptr, col, weights=None, k: int = 8, tol: float = 0.05,
                  max_iter: int = 20, seed: int = 0, mode: str = "det", rho: int = 8,
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
                  stream=None, workspace=None, rule: str = "mg", rescan: bool = False,
-                 hub_shared: bool = False, capture: bool = False):
+                 hub_shared: bool = False, capture: bool = False, shared_vars: bool = False):
         import torch
 
         def usable(t):  # device memory, or pinned host memory the device maps
             return t.is_cuda or (t.device.type == "cpu" and t.is_pinned())
 
-        for t, dt in ((row_ptr, torch.int32), (col, torch.int32)):
-            if t.dtype != dt or not usable(t) or not t.is_contiguous():
-                raise ValueError("row_ptr / col must be contiguous int32 CUDA (or pinned) tensors")
+        for t, dts in ((row_ptr, (torch.int32, torch.int64)), (col, (torch.int32,))):
+            if t.dtype not in dts or not usable(t) or not t.is_contiguous():
+                raise ValueError("row_ptr (int32 / int64) and col (int32) must be contiguous "
+                                 "CUDA (or pinned) tensors")
         if weights is not None and (weights.dtype != torch.float32 or not usable(weights)
                                     or not weights.is_contiguous()):
             raise ValueError("weights must be a contiguous float32 CUDA (or pinned) tensor")
@@ -330,6 +338,7 @@ class LPA:
         cfg = lpa_config_default()
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
                      | (LPA_RESCAN if rescan else 0) | (LPA_HUB_SHARED if hub_shared else 0)
+                     | (LPA_SHARED_VARS if shared_vars else 0)
                      | (LPA_CAPTURE if capture else 0))
         cfg.rho = rho
         if stream is None:
@@ -349,7 +358,7 @@ class LPA:
         with torch.cuda.device(self.device):
             self.h = lpa_init(self.n, self.nnz, row_ptr.data_ptr(), col.data_ptr() if self.nnz else 0,
                               weights.data_ptr() if weights is not None else None, k, tol,
-                              max_iter, seed, cfg)
+                              max_iter, seed, cfg, offsets64=row_ptr.dtype == torch.int64)
 
     def step(self) -> Tuple[int, bool]:
         return lpa_step(self.h)
@@ -432,11 +441,12 @@ class Batch:
 
     def __init__(self, capacity: int, k: int = 8, mode: str = "det", check_every: int = 0,
                  stream=None, device=None, rule: str = "mg", rescan: bool = False,
-                 hub_shared: bool = False, capture: bool = False):
+                 hub_shared: bool = False, capture: bool = False, shared_vars: bool = False):
         import torch
         cfg = lpa_config_default()
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_RESCAN if rescan else 0)
-                     | (LPA_HUB_SHARED if hub_shared else 0) | (LPA_CAPTURE if capture else 0))
+                     | (LPA_HUB_SHARED if hub_shared else 0) | (LPA_CAPTURE if capture else 0)
+                     | (LPA_SHARED_VARS if shared_vars else 0))
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream

@@ -34,7 +34,8 @@ def test_config_default():
 
 def _init(**kw):
     L = lpa.load()
-    g = lpa.LpaGraph(kw.get("n", 4), kw.get("nnz", 0), kw.get("rp", 0), kw.get("col", 0))
+    g = lpa.LpaGraph(kw.get("n", 4), kw.get("nnz", 0), kw.get("rp", 0), kw.get("col", 0),
+                     kw.get("rp64", 0))
     cfg = lpa.lpa_config_default()
     for k, v in kw.get("cfg", {}).items():
         setattr(cfg, k, v)
@@ -51,6 +52,8 @@ def _init(**kw):
     (dict(n=4, rp=0), lpa.LPA_ERR_ARG),              # null row_ptr with n > 0
     (dict(n=0, nnz=3), lpa.LPA_ERR_ARG),
     (dict(n=4, rp=8, nnz=2**31), lpa.LPA_ERR_ARG),   # nnz beyond int32 offsets
+    (dict(n=4, rp=8, rp64=16), lpa.LPA_ERR_ARG),     # both offset widths given
+    (dict(n=4, rp64=16, nnz=2**62), lpa.LPA_ERR_ARG),  # beyond the largest graph
     (dict(n=4, rp=8, tol=-0.1), lpa.LPA_ERR_ARG),
     (dict(n=4, rp=8, tol=float("nan")), lpa.LPA_ERR_ARG),
     (dict(n=4, rp=8, max_iter=-1), lpa.LPA_ERR_ARG),
@@ -105,9 +108,18 @@ def test_bm_paper_rule_flag():
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
     assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
-    cfg.flags = lpa.LPA_MODE_DET | 0x2000
+    cfg.flags = lpa.LPA_MODE_DET | 0x4000
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_UNSUPPORTED
+    # shared variables instead of votes: det sketch rule without double scan only
+    for bad in (lpa.LPA_MODE_ASYNC | lpa.LPA_SHARED_VARS,
+                lpa.LPA_MODE_DET | lpa.LPA_SHARED_VARS | lpa.LPA_RESCAN,
+                lpa.LPA_MODE_DET | lpa.LPA_SHARED_VARS | lpa.LPA_RULE_BM_PAPER):
+        cfg.flags = bad
+        assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+            lpa.LPA_ERR_ARG
+    cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_SHARED_VARS
+    assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
     # one shared sketch per hub: async sketch rule without double scan only
     for bad in (lpa.LPA_MODE_DET | lpa.LPA_HUB_SHARED,
                 lpa.LPA_MODE_ASYNC | lpa.LPA_HUB_SHARED | lpa.LPA_RESCAN,
@@ -126,3 +138,26 @@ def test_bm_paper_rule_flag():
     b = ctypes.c_void_p()
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
     assert L.lpa_batch_create(4, 8, ctypes.byref(cfg), ctypes.byref(b)) == lpa.LPA_ERR_ARG
+
+
+def test_offsets64_workspace_bounds():
+    """The workspace size does not depend on the offset width; graphs of
+    2^31 or more entries are sized, up to 2^62 entries, as long as the
+    async hub segments stay below 2^30."""
+    L = lpa.load()
+    out = ctypes.c_size_t(0)
+    cfg = lpa.lpa_config_default()
+    for flags in (lpa.LPA_MODE_DET, lpa.LPA_MODE_ASYNC):
+        cfg.flags = flags
+        assert L.lpa_workspace_bytes(1 << 25, 1 << 32, 8, 20, ctypes.byref(cfg),
+                                     ctypes.byref(out)) == lpa.LPA_OK
+        assert out.value > (1 << 25) * 9
+        assert L.lpa_workspace_bytes(1 << 25, 1 << 62, 8, 20, ctypes.byref(cfg),
+                                     ctypes.byref(out)) == lpa.LPA_ERR_ARG
+    cfg.flags = lpa.LPA_MODE_ASYNC
+    cfg.lane_max_degree = 1  # one segment per entry: far too many
+    assert L.lpa_workspace_bytes(1 << 25, 1 << 31, 8, 20, ctypes.byref(cfg),
+                                 ctypes.byref(out)) == lpa.LPA_ERR_UNSUPPORTED
+    cfg.flags = lpa.LPA_MODE_DET  # no segments in det mode
+    assert L.lpa_workspace_bytes(1 << 25, 1 << 31, 8, 20, ctypes.byref(cfg),
+                                 ctypes.byref(out)) == lpa.LPA_OK

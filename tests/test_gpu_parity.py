@@ -33,10 +33,11 @@ def to_dev(g):
 
 
 def gpu_run(g, k, mode="det", tol=0.05, max_iter=20, rho=8, lane_max_degree=0, rule="mg",
-            rescan=False):
+            rescan=False, shared_vars=False):
     rp, col, w = to_dev(g)
     s = lpa.LPA(rp, col, w, k=k, tol=tol, max_iter=max_iter, rho=rho, mode=mode,
-                lane_max_degree=lane_max_degree, rule=rule, rescan=rescan)
+                lane_max_degree=lane_max_degree, rule=rule, rescan=rescan,
+                shared_vars=shared_vars)
     it = s.run()
     labels = s.labels(device=False)
     dn, sc = s.trace()
@@ -429,3 +430,39 @@ def test_hub_shared_validity(lane_max):
     with pytest.raises(lpa.LpaError):
         rp, col, w = to_dev(graph("sbm1-s1"))
         lpa.LPA(rp, col, w, k=8, mode="det", hub_shared=True)
+
+
+# ---- shared variables instead of votes (LPA_SHARED_VARS, Section 4.1) ----
+
+@pytest.mark.parametrize("name", ["two-cliques-10", "sbm1-s2-w", "rmat14-w", "star5000",
+                                  "rmat10-selfloops", "sbm1-iso"])
+@pytest.mark.parametrize("k", KS)
+@pytest.mark.parametrize("lane_max", [0, 1, 16])
+def test_shared_vars_det_parity(name, k, lane_max):
+    # lane_max 1 and 16 send (nearly) every vertex through the
+    # one-wavefront-per-vertex path whose lanes talk through LDS variables
+    check_det(graph(name), k, lane_max_degree=lane_max, shared_vars=True)
+
+
+def test_shared_vars_batch_and_rejections():
+    gs = [graph("sbm1-s1"), graph("rmat14-w"), graph("star5000")]
+    solvers = []
+    for g in gs:
+        rp, col, w = to_dev(g)
+        solvers.append(lpa.LPA(rp, col, w, k=8, shared_vars=True, lane_max_degree=16))
+    batch = lpa.Batch(len(gs), k=8, shared_vars=True)
+    batch.run(solvers)
+    for g, s in zip(gs, solvers):
+        assert np.array_equal(s.labels(device=False), oracle.lpa_run(g.row_ptr, g.col, g.w, k=8)[0])
+    rp, col, w = to_dev(gs[0])
+    plain = lpa.LPA(rp, col, w, k=8)
+    with pytest.raises(lpa.LpaError):
+        batch.run([plain])  # a handle without the flag cannot join
+    for kw in (dict(mode="async"), dict(rescan=True), dict(k=1, rule="bm_paper")):
+        args = dict(k=8, shared_vars=True)
+        args.update(kw)
+        with pytest.raises(lpa.LpaError) as ei:
+            lpa.LPA(rp, col, w, **args)
+        assert ei.value.code == lpa.LPA_ERR_ARG
+    for x in solvers + [plain, batch]:
+        x.close()

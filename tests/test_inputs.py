@@ -90,3 +90,31 @@ def test_permuted_is_isomorphic():
     edges = {(i, int(j)): float(x) for i in range(h.n)
              for j, x in zip(h.col[h.row_ptr[i]:h.row_ptr[i + 1]], h.w[h.row_ptr[i]:h.row_ptr[i + 1]])}
     assert all(edges[(j, i)] == x for (i, j), x in edges.items())
+
+
+def test_ring_hubs_closed_form():
+    """The device builder (run here with torch on the CPU) and the per-row
+    recomputation give the same CSR, which is symmetric with matching
+    weights, has the stated degrees and no self-loops or duplicates."""
+    torch = pytest.importorskip("torch")
+    from paper_2411_19901_amd import inputs
+    L, H, r, seed = 1500, 9, 4, 11
+    rp, col, w = inputs.ring_hubs_device(L, H, r, seed, "cpu", chunk=256)
+    rp, col, w = rp.numpy(), col.numpy(), w.numpy()
+    n = L + H
+    assert rp.dtype == np.int64 and rp[-1] == L * (2 * r + 2) == len(col) == len(w)
+    rps, cols, ws = inputs.ring_hubs_rows(L, H, r, seed, np.arange(n))
+    assert np.array_equal(rp, rps) and np.array_equal(col, cols) and np.array_equal(w, ws)
+    deg = np.diff(rp)
+    assert np.all(deg[:L] == 2 * r + 1)
+    assert deg[L:].sum() == L and deg[L:].max() - deg[L:].min() <= 1
+    assert np.all((w > 0) & (w <= 1)) and np.all(w * 2.0 ** 24 == np.round(w * 2.0 ** 24))
+    edges = {}
+    for i in range(n):
+        row = col[rp[i]:rp[i + 1]]
+        assert len(set(row.tolist())) == len(row) and i not in row
+        for j, x in zip(row, w[rp[i]:rp[i + 1]]):
+            edges[(i, int(j))] = float(x)
+    assert all(edges[(j, i)] == x for (i, j), x in edges.items())
+    with pytest.raises(ValueError):
+        inputs.ring_hubs_offsets(5, 1, 2)
