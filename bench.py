@@ -327,7 +327,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--graph", default="rmat", choices=["rmat", "grid", "sbm1"])
+    ap.add_argument("--graph", default="rmat", choices=["rmat", "grid", "sbm1", "ring"],
+                    help="ring: the closed-form ring-plus-hubs graph of 2.23e9 CSR entries "
+                         "(L = 36M lane vertices of degree 61, 64 hubs), built in device "
+                         "memory with int64 row offsets")
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--weights", default="uniform", choices=["uniform", "unit"])
     ap.add_argument("--k", type=int, default=8)
@@ -344,6 +347,11 @@ def main():
     ap.add_argument("--hub-shared", action="store_true",
                     help="one shared LDS sketch per high-degree vertex instead of merged "
                          "partial sketches (async ablation)")
+    ap.add_argument("--offsets64", action="store_true",
+                    help="hand the row offsets over as int64 (64-bit CSR positions)")
+    ap.add_argument("--shared-vars", action="store_true",
+                    help="det hub path with LDS shared variables instead of wavefront votes "
+                         "(LPA_SHARED_VARS)")
     ap.add_argument("--rescan", action="store_true",
                     help="double scan: re-weight the sketch's labels exactly in a second pass")
     ap.add_argument("--rule", default="mg", choices=["mg", "bm_paper"],
@@ -403,24 +411,41 @@ def main():
             args.mode = "det"
         return bench_serve(args)
     dev = torch.device("cuda:0")
-    g, gname = build_graph(args)
+    if args.graph == "ring":
+        from types import SimpleNamespace
+        from paper_2411_19901_amd import inputs
+        L, H, r = 36_000_000, 64, 30
+        t = time.perf_counter()
+        rp, col, w = inputs.ring_hubs_device(L, H, r, 2024, dev)
+        torch.cuda.synchronize()
+        g = SimpleNamespace(n=L + H, nnz=int(rp[-1]))
+        gname = f"ring{L // 1_000_000}M-h{H}-r{r}-wU(0,1]"
+        h2d_s = 0.0
+        args.offsets64 = True
+        args.no_cpu_baseline = True  # the graph exists only in device memory
+        log(f"[bench] built {gname} on the device: n={g.n} nnz={g.nnz} "
+            f"in {time.perf_counter() - t:.1f}s")
+    else:
+        g, gname = build_graph(args)
     if args.rule == "bm_paper":
         args.k = 1
     rule_tag = ((f"k{args.k}" if args.rule == "mg" else "bm-paper") + ("-rescan" if args.rescan else "")
-                + ("-hubshared" if args.hub_shared else ""))
-    workload = f"{gname}-{args.mode}-{rule_tag}"
+                + ("-hubshared" if args.hub_shared else "")
+                + ("-sharedvars" if args.shared_vars else ""))
+    workload = f"{gname}-{args.mode}-{rule_tag}" + ("-off64" if args.offsets64 else "")
 
-    t = time.perf_counter()
-    if args.host_csr:
-        place = lambda a: torch.from_numpy(a).pin_memory()  # noqa: E731
-        workload += "-hostcsr"
-    else:
-        place = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
-    rp = place(g.row_ptr)
-    col = place(g.col)
-    w = place(g.w) if g.w is not None else None
-    torch.cuda.synchronize()
-    h2d_s = time.perf_counter() - t
+    if args.graph != "ring":
+        t = time.perf_counter()
+        if args.host_csr:
+            place = lambda a: torch.from_numpy(a).pin_memory()  # noqa: E731
+            workload += "-hostcsr"
+        else:
+            place = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+        rp = place(g.row_ptr.astype(np.int64) if args.offsets64 else g.row_ptr)
+        col = place(g.col)
+        w = place(g.w) if g.w is not None else None
+        torch.cuda.synchronize()
+        h2d_s = time.perf_counter() - t
     stream = torch.cuda.current_stream(dev)
     tuned = None
     if args.autotune:
@@ -435,7 +460,7 @@ def main():
     t = time.perf_counter()
     solver = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
                      mode=args.mode, lane_max_degree=args.lane_max_degree, rule=args.rule,
-                     rescan=args.rescan, hub_shared=args.hub_shared,
+                     rescan=args.rescan, hub_shared=args.hub_shared, shared_vars=args.shared_vars,
                      check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t) * 1e3
@@ -484,8 +509,12 @@ def main():
     achieved = kernel_bytes / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else 0.0
     digest = source_digest()
     kk = args.k if args.rule == "mg" else 0  # kernel template: 0 = the vote of Algorithm 3
-    kname = (f"lpa::k_move{'_rescan' if args.rescan else ''}"
-             f"<{kk}, {'true' if args.mode == 'async' else 'false'}>")
+    wide = "true" if args.offsets64 else "false"
+    if args.shared_vars:
+        kname = f"lpa::k_move_sv<{kk}, {wide}>"
+    else:
+        kname = (f"lpa::k_move{'_rescan' if args.rescan else ''}"
+                 f"<{kk}, {'true' if args.mode == 'async' else 'false'}, {wide}>")
     traffic = traffic_from_profiles(kname,
                                     workload, digest)
     result = {
@@ -504,7 +533,7 @@ def main():
         "config": {"workload": workload, "n": g.n, "nnz": g.nnz, "k": args.k, "rule": args.rule,
                    "lane_max_degree": args.lane_max_degree or (1024 if args.mode == "async"
                                                                 else 4096),
-                   "rescan": args.rescan,
+                   "rescan": args.rescan, "offsets": 64 if args.offsets64 else 32,
                    "mode": args.mode,
                    "tol": args.tol, "max_iter": args.max_iter, "rho": 8,
                    "step": "lpa_reset + lpa_run (all iterations to convergence)"},
