@@ -37,6 +37,18 @@ __host__ __device__ inline int degree_class(int d, int lane_max) {
   return kHubClasses + kLaneBuckets + (kLaneExact - d);
 }
 
+// Device pointers into device or mapped host memory, never LDS or scratch.
+// Typed as the global address space so that the compiler emits global
+// (not flat) loads and stores: flat accesses may alias LDS, which forbids
+// moving them across the LDS staging and serialises a wavefront's loads.
+#define LPA_GLOBAL __attribute__((address_space(1)))
+template <class T>
+using gptr = T LPA_GLOBAL *;
+template <class T>
+__host__ __device__ __forceinline__ gptr<T> as_global(T *p) {
+  return (gptr<T>)p;
+}
+
 // CSR row offsets, 32- or 64-bit: exactly one pointer is set for a graph
 // with vertices.  The choice is the same for every vertex of a graph, so
 // the test is a uniform branch.
@@ -44,7 +56,7 @@ struct RowPtr {
   const int32_t *p32;
   const int64_t *p64;
   __device__ __forceinline__ long long operator[](long long i) const {
-    return p64 ? (long long)p64[i] : (long long)p32[i];
+    return p64 ? (long long)as_global(p64)[i] : (long long)as_global(p32)[i];
   }
 };
 
@@ -110,22 +122,22 @@ struct Launch {
 struct MoveArgs {
   int32_t n;
   RowPtr row_ptr;
-  const int32_t *col;
-  const float *w;
-  int32_t *C;              // labels read this iteration (async: read/write)
-  int32_t *Cn;             // labels written this iteration (async: == C)
-  uint8_t *act_cur;        // unprocessed flags read (and cleared) this iteration
-  uint8_t *act_next;       // flags set for the next iteration (async: == act_cur)
-  const int32_t *order;
+  gptr<const int32_t> col;
+  gptr<const float> w;
+  gptr<int32_t> C;         // labels read this iteration (async: read/write)
+  gptr<int32_t> Cn;        // labels written this iteration (async: == C)
+  gptr<uint8_t> act_cur;   // unprocessed flags read (and cleared) this iteration
+  gptr<uint8_t> act_next;  // flags set for the next iteration (async: == act_cur)
+  gptr<const int32_t> order;
   int32_t n_hubs;
   int32_t n_lane;
   int32_t seg_len;
   int32_t n_seg;
-  const int32_t *seg_hub;
-  const int32_t *hub_pbase;
-  uint8_t *hub_act;
-  int32_t *part_key;
-  float *part_val;
+  gptr<const int32_t> seg_hub;
+  gptr<const int32_t> hub_pbase;
+  gptr<uint8_t> hub_act;
+  gptr<int32_t> part_key;
+  gptr<float> part_val;
   int32_t iter;
   int32_t pickless;
 };

@@ -50,7 +50,7 @@ __device__ __forceinline__ Pos row_at(const RowPtr &rp, int v) {
   if constexpr (sizeof(Pos) == 8)
     return rp[v];
   else
-    return rp.p32[v];
+    return as_global(rp.p32)[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -166,29 +166,44 @@ struct SketchOf<0> {
 // Slots stored per partial sketch.
 constexpr int slots_of(int K) { return K == 0 ? 1 : K; }
 
-// Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
-// nothing).  All lanes of the wavefront must call it together.
 // Load one staging step of TW entries for each of the 64 rows (TW <= T):
 // slot i * 64 + lane holds entry t0 + j of row r, (r, j) = (slot / TW,
-// slot % TW), stored at r * (TW + 1) + j.
+// slot % TW), stored at r * (TW + 1) + j.  The slots are taken kLoadBatch
+// at a time in three phases (column indices, weights, gathered labels), so
+// that each phase's loads are in flight together; a slot past its row's end
+// issues no load and is stored as padding (label -1, weight 0).
+constexpr int kLoadBatch = 4;
+
 template <int TW, int T, class Pos>
 __device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T, Pos> &st, int lane, int t0) {
+  constexpr int B = TW < kLoadBatch ? TW : kLoadBatch;
 #pragma unroll
-  for (int i = 0; i < TW; ++i) {
-    const int slot = i * kWave + lane;
-    const int r = slot / TW, j = slot % TW;
-    const int p = t0 + j;
-    int lab = -1;
-    float x = 0.0f;
-    if (p < st.len[r]) {
-      const Pos e = st.beg[r] + p;
-      const int c = __builtin_nontemporal_load(a.col + e);
-      x = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
-      if (c == st.self[r]) x = 0.0f;
-      lab = a.C[c];
+  for (int i0 = 0; i0 < TW; i0 += B) {
+    bool ok[B];
+    Pos e[B];
+    int c[B], lab[B];
+    float x[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int slot = (i0 + b) * kWave + lane;
+      const int r = slot / TW, j = slot % TW;
+      ok[b] = t0 + j < st.len[r];
+      e[b] = st.beg[r] + (t0 + j);
     }
-    st.lab[r * (TW + 1) + j] = lab;
-    st.w[r * (TW + 1) + j] = x;
+#pragma unroll
+    for (int b = 0; b < B; ++b) c[b] = ok[b] ? __builtin_nontemporal_load(a.col + e[b]) : -1;
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      x[b] = !ok[b] ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e[b]) : 1.0f);
+#pragma unroll
+    for (int b = 0; b < B; ++b) lab[b] = ok[b] ? a.C[c[b]] : -1;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int slot = (i0 + b) * kWave + lane;
+      const int r = slot / TW, j = slot % TW;
+      st.lab[r * (TW + 1) + j] = lab[b];
+      st.w[r * (TW + 1) + j] = c[b] == st.self[r] ? 0.0f : x[b];
+    }
   }
 }
 
@@ -690,22 +705,22 @@ __device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
   MoveArgs a;
   a.n = d.n;
   a.row_ptr = d.row_ptr;
-  a.col = d.col;
-  a.w = d.w;
-  a.C = d.C[iter & 1];
-  a.Cn = d.C[(iter + 1) & 1];
-  a.act_cur = d.act[iter & 1];
-  a.act_next = d.act[(iter + 1) & 1];
-  a.order = d.order;
+  a.col = as_global(d.col);
+  a.w = as_global(d.w);
+  a.C = as_global(d.C[iter & 1]);
+  a.Cn = as_global(d.C[(iter + 1) & 1]);
+  a.act_cur = as_global(d.act[iter & 1]);
+  a.act_next = as_global(d.act[(iter + 1) & 1]);
+  a.order = as_global(d.order);
   a.n_hubs = d.n_hubs;
   a.n_lane = d.n_lane;
   a.seg_len = d.seg_len;
   a.n_seg = d.hub_shared ? 0 : d.n_seg;  // shared hubs: no segment units in k_move
-  a.seg_hub = d.seg_hub;
-  a.hub_pbase = d.hub_pbase;
-  a.hub_act = d.hub_act;
-  a.part_key = d.part_key;
-  a.part_val = d.part_val;
+  a.seg_hub = as_global(d.seg_hub);
+  a.hub_pbase = as_global(d.hub_pbase);
+  a.hub_act = as_global(d.hub_act);
+  a.part_key = as_global(d.part_key);
+  a.part_val = as_global(d.part_val);
   a.iter = iter;
   a.pickless = (d.rho > 0 && iter % d.rho == 0) ? 1 : 0;
   return a;
@@ -771,9 +786,13 @@ __device__ __forceinline__ void move_body(const Launch &L) {
 template <bool W>
 using PosOf = typename std::conditional<W, long long, int>::type;
 
-// One iteration's label moves (single scan) ...
+// One iteration's label moves (single scan) ...  With 32-bit positions and
+// up to k = 8 the kernel fits 128 registers, which keeps four wavefronts
+// per SIMD for the gathers; the other instantiations are left to the
+// compiler (forcing four would spill).
 template <int K, bool ASYNC, bool W>
-__global__ __launch_bounds__(kBlock) void k_move(Launch L) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(!W && K <= 8 ? 4 : 1)))
+void k_move(Launch L) {
   move_body<K, ASYNC, false, PosOf<W>>(L);
 }
 
