@@ -347,6 +347,11 @@ def main():
     ap.add_argument("--hub-shared", action="store_true",
                     help="one shared LDS sketch per high-degree vertex instead of merged "
                          "partial sketches (async ablation)")
+    ap.add_argument("--stream-csr", action="store_true",
+                    help="keep the CSR in pinned host memory and stream it to the device in "
+                         "slices every iteration (LPA_STREAM_CSR, det mode)")
+    ap.add_argument("--stream-chunk-kib", type=int, default=0,
+                    help="slice size for --stream-csr in KiB of column indices (0 = 256 MiB)")
     ap.add_argument("--offsets64", action="store_true",
                     help="hand the row offsets over as int64 (64-bit CSR positions)")
     ap.add_argument("--shared-vars", action="store_true",
@@ -436,9 +441,9 @@ def main():
 
     if args.graph != "ring":
         t = time.perf_counter()
-        if args.host_csr:
+        if args.host_csr or args.stream_csr:
             place = lambda a: torch.from_numpy(a).pin_memory()  # noqa: E731
-            workload += "-hostcsr"
+            workload += "-stream" if args.stream_csr else "-hostcsr"
         else:
             place = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
         rp = place(g.row_ptr.astype(np.int64) if args.offsets64 else g.row_ptr)
@@ -461,6 +466,7 @@ def main():
     solver = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
                      mode=args.mode, lane_max_degree=args.lane_max_degree, rule=args.rule,
                      rescan=args.rescan, hub_shared=args.hub_shared, shared_vars=args.shared_vars,
+                     stream_csr=args.stream_csr, stream_chunk_kib=args.stream_chunk_kib,
                      check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t) * 1e3

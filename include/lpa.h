@@ -121,6 +121,23 @@ typedef enum lpa_status {
  * and atomic minimums (the shared-variable protocol of Algorithm 5) instead
  * of wavefront votes.  Results are identical; only the speed differs. */
 #define LPA_SHARED_VARS 0x2000u
+/* Stream the graph from host memory (LPA_MODE_DET; LPA_ERR_ARG otherwise):
+ * col_idx and the weights must be pinned host memory (LPA_PTR_HOST; the
+ * row offsets may be host or device memory and are copied to the device
+ * once).  lpa_init cuts the vertices into consecutive id ranges whose rows
+ * fill at most stream_chunk_kib KiB of column indices (a range is one
+ * vertex when that vertex alone is larger) and bins each range by degree.
+ * Every iteration then copies the ranges' rows into four device buffers in
+ * turn with DMA on a stream of the handle's own; each range's move kernel
+ * starts once its copy has landed, on one of four compute streams (the
+ * caller's and three of the handle's), so copies and up to four ranges'
+ * kernels overlap.  The synchronous update makes the labels independent of
+ * the cut and of that overlap: results are identical to the unstreamed
+ * run.  Device memory: the library state, a second degree order (4 B per
+ * vertex), the row offsets and the four buffers; not the graph.  lpa_run checks convergence after every
+ * iteration; LPA_CAPTURE and lpa_batch_* do not apply (batches refuse such
+ * handles with LPA_ERR_ARG). */
+#define LPA_STREAM_CSR 0x4000u
 
 /* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji).  Row
  * offsets are given either as int32 (row_ptr, graphs of fewer than 2^31 - 1
@@ -140,7 +157,8 @@ typedef struct lpa_graph {
 typedef struct lpa_config {
   uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC,
                               | LPA_VALIDATE, | LPA_RULE_BM_PAPER, | LPA_RESCAN,
-                              | LPA_HUB_SHARED, | LPA_CAPTURE, | LPA_SHARED_VARS */
+                              | LPA_HUB_SHARED, | LPA_CAPTURE, | LPA_SHARED_VARS,
+                              | LPA_STREAM_CSR */
   int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per
@@ -158,7 +176,11 @@ typedef struct lpa_config {
                               lpa_workspace_bytes); NULL = lpa_init allocates
                               one block itself.  Borrowed like the graph. */
   size_t workspace_bytes;
-  int32_t reserved[4];     /* must be zero */
+  int32_t stream_chunk_kib; /* LPA_STREAM_CSR: rows copied per slice, in
+                              KiB of column indices (the weights double
+                              it); 0 = 262144 (256 MiB).  Ignored
+                              otherwise. */
+  int32_t reserved[3];     /* must be zero */
 } lpa_config;
 
 typedef struct lpa_handle lpa_handle;

@@ -75,9 +75,10 @@ __global__ void k_check_labels(const int32_t *lab, int n, int *bad) {
 }
 
 // --- degree binning: histogram -> exclusive scan -> scatter ---------------
-// Stable degree binning (once per graph): vertices ordered by degree class
-// (decreasing degree), increasing id within a class; isolated vertices are
-// left out.  Block b owns the ids [b * kBinIds, (b + 1) * kBinIds).
+// Stable degree binning (once per graph, or once per id range of a streamed
+// graph): vertices v0 .. v0 + n - 1 ordered by degree class (decreasing
+// degree), increasing id within a class; isolated vertices are left out.
+// Block b owns the ids v0 + [b * kBinIds, (b + 1) * kBinIds).
 //   1. k_bin_count: counts[c * nblk + b] = vertices of class c in block b;
 //   2. k_scan_*: exclusive prefix sum over counts in (class, block) order,
 //      which is each block's first position for each class;
@@ -90,12 +91,13 @@ constexpr int64_t kMaxSegs = (int64_t)1 << 30;
 constexpr int kBinIds = 4096;
 constexpr int kScanChunk = 4096;  // entries per block of the prefix sum
 
-__global__ void k_bin_count(int n, RowPtr rp, int lane_max, int nblk, unsigned *counts) {
+__global__ void k_bin_count(int v0, int n, RowPtr rp, int lane_max, int nblk, unsigned *counts) {
   __shared__ unsigned cnt[kClasses];
   for (int c = threadIdx.x; c < kClasses; c += blockDim.x) cnt[c] = 0;
   __syncthreads();
-  const int v0 = blockIdx.x * kBinIds;
-  for (int v = v0 + threadIdx.x; v < v0 + kBinIds && v < n; v += blockDim.x) {
+  const int b0 = blockIdx.x * kBinIds;
+  for (int u = b0 + threadIdx.x; u < b0 + kBinIds && u < n; u += blockDim.x) {
+    const int v = v0 + u;
     const int d = (int)(rp[v + 1] - rp[v]);
     if (d > 0) atomicAdd(&cnt[degree_class(d, lane_max)], 1u);
   }
@@ -160,18 +162,19 @@ __global__ void k_scan_add(unsigned *x, size_t count, const unsigned *sums) {
 // Place every vertex of block b at its class's next position, in id order.
 // 256 threads walk the block's ids 256 at a time; the four wavefronts take
 // turns so that lower ids are placed first.
-__global__ __launch_bounds__(256) void k_bin_place(int n, RowPtr rp, int lane_max, int nblk,
+__global__ __launch_bounds__(256) void k_bin_place(int v0, int n, RowPtr rp, int lane_max, int nblk,
                                                    const unsigned *offsets, int32_t *order) {
   __shared__ unsigned next[kClasses];
   for (int c = threadIdx.x; c < kClasses; c += blockDim.x) next[c] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
-  const int v0 = blockIdx.x * kBinIds;
+  const int b0 = blockIdx.x * kBinIds;
   for (int r = 0; r < kBinIds; r += 256) {
-    const int v = v0 + r + (int)threadIdx.x;
+    const int u = b0 + r + (int)threadIdx.x;
+    const int v = v0 + u;
     int cls = -1;
-    if (v < n) {
+    if (u < n) {
       const int d = (int)(rp[v + 1] - rp[v]);
       if (d > 0) cls = degree_class(d, lane_max);
     }
@@ -406,6 +409,32 @@ struct lpa_handle {
   std::string err;
   std::vector<hipEvent_t> ev_beg, ev_end;
   lpa_batch *self = nullptr;  // batch of one used by lpa_step / lpa_run
+
+  // LPA_STREAM_CSR: the graph stays in pinned host memory; every iteration
+  // copies the rows of one id range after another into kBufs device
+  // buffers in turn; range p runs on compute stream p % kBufs (stream 0 is
+  // the handle's), so the move kernels of up to kBufs ranges overlap
+  struct Streamed {
+    static constexpr int kBufs = 4;
+    bool on = false;
+    hipStream_t copy = nullptr;        // DMA stream (default priority)
+    hipStream_t cs[kBufs] = {};        // compute streams; cs[0] = the handle's
+    hipEvent_t copied[kBufs] = {}, done[kBufs] = {};
+    hipEvent_t start = nullptr;        // the previous iteration's stop test is done
+    const int32_t *host_col = nullptr;
+    const float *host_w = nullptr;
+    void *dev = nullptr;  // row offsets, second order, descriptors, prefixes, buffers
+    size_t dev_bytes = 0;
+    int32_t *col_buf[kBufs] = {};
+    float *w_buf[kBufs] = {};
+    std::vector<int32_t> first;          // [ranges + 1] first vertex of each range
+    std::vector<int64_t> base, entries;  // per range: first CSR entry, entries
+    int32_t *order = nullptr;            // device [n]: vertices of each range by degree
+    std::vector<int32_t> items;          // per range: move work items
+    GraphDesc *desc = nullptr;           // device [ranges]
+    int32_t *prefix = nullptr;           // device [ranges][2] = {0, items}
+    int grid_cap = 1;
+  } sm;
 };
 
 namespace {
@@ -494,6 +523,7 @@ int check_k(int k, uint32_t flags) {
   if ((flags & LPA_SHARED_VARS) &&
       ((flags & LPA_MODE_MASK) != LPA_MODE_DET || (flags & (LPA_RULE_BM_PAPER | LPA_RESCAN))))
     return LPA_ERR_ARG;
+  if ((flags & LPA_STREAM_CSR) && (flags & LPA_MODE_MASK) != LPA_MODE_DET) return LPA_ERR_ARG;
   return LPA_OK;
 }
 
@@ -668,6 +698,7 @@ int batch_load(lpa_batch *b, lpa_handle *const *hs, int count) {
     if (!h) return LPA_ERR_ARG;
     wide = wide || h->row_ptr.p64 != nullptr;
     if (h->poisoned) return LPA_ERR_HIP;
+    if (h->sm.on && b != h->self) return LPA_ERR_ARG;  // streamed graphs run alone
     if (kernel_k(h->k, h->flags) != b->k || ((h->flags & LPA_RESCAN) != 0) != b->rescan ||
         ((h->flags & LPA_HUB_SHARED) != 0) != b->hub_shared ||
         ((h->flags & LPA_SHARED_VARS) != 0) != b->shared_vars ||
@@ -861,16 +892,16 @@ int lpa_pointer_location(const void *ptr, int *location) {
 }
 
 static int check_config(const lpa_config &cfg) {
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (cfg.reserved[i] != 0) return LPA_ERR_ARG;
   if (cfg.rho < 0 || cfg.lane_max_degree < 0 || cfg.lane_max_degree > 65536 ||
-      cfg.check_every < 0)
+      cfg.check_every < 0 || cfg.stream_chunk_kib < 0)
     return LPA_ERR_ARG;
   const uint32_t mode = cfg.flags & LPA_MODE_MASK;
   if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
   if ((cfg.flags &
        ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN | LPA_HUB_SHARED |
-         LPA_CAPTURE | LPA_SHARED_VARS)) != 0)
+         LPA_CAPTURE | LPA_SHARED_VARS | LPA_STREAM_CSR)) != 0)
     return LPA_ERR_UNSUPPORTED;
   if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
   return LPA_OK;
@@ -896,12 +927,260 @@ int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter, const lpa_c
   return LPA_OK;
 }
 
+namespace {
+
+// Degree-bin the vertices [v0, v0 + nr) into order[0 .. hubs + lanes): the
+// binning kernels above, with the label buffer C[0] as their count matrix
+// (before the labels are initialised) and synchronising once for the
+// totals.
+hipError_t bin_range(lpa_handle *h, int v0, int nr, int32_t *order, int *hubs, int *lanes) {
+  *hubs = *lanes = 0;
+  if (nr <= 0) return hipSuccess;
+  const int nblk = (nr + kBinIds - 1) / kBinIds;
+  const size_t cells = (size_t)kClasses * nblk;
+  const int nchunks = (int)((cells + kScanChunk - 1) / kScanChunk);
+  unsigned *counts = (unsigned *)h->desc.C[0];
+  hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, h->stream, v0, nr, h->row_ptr,
+                     h->lane_max, nblk, counts);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(nchunks), dim3(256), 0, h->stream, counts, cells,
+                     (unsigned *)h->hist);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, h->stream, (unsigned *)h->hist, nchunks,
+                     counts, nblk, h->st->totals);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, h->stream,
+                     counts, cells, (const unsigned *)h->hist);
+  hipLaunchKernelGGL(k_bin_place, dim3(nblk), dim3(256), 0, h->stream, v0, nr, h->row_ptr,
+                     h->lane_max, nblk, (const unsigned *)counts, order);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int totals[4] = {0, 0, 0, 0};
+  if ((e = hipMemcpyAsync(totals, h->st->totals, sizeof(totals), hipMemcpyDeviceToHost,
+                          h->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+    return e;
+  *hubs = totals[0];
+  *lanes = totals[1];
+  return hipSuccess;
+}
+
+// --- LPA_STREAM_CSR ---------------------------------------------------------
+// Cut the vertices into id ranges of at most the chunk size in CSR entries
+// (one vertex when it alone is larger), copy the row offsets to the device
+// (h->row_ptr then points there) and allocate the device side: a second
+// degree order, one descriptor and prefix pair per range, two slice buffers
+// sized for the largest range, a copy stream and its events.
+int stream_prepare(lpa_handle *h, const lpa_graph *g, const lpa_config &cfg) {
+  lpa_handle::Streamed &S = h->sm;
+  S.on = true;
+  S.host_col = g->col_idx;
+  S.host_w = h->w;
+  const int n = h->n;
+  std::vector<int64_t> rp((size_t)n + 1);
+  if (g->row_ptr64) {
+    HIP_TRY(h, hipMemcpy(rp.data(), g->row_ptr64, ((size_t)n + 1) * 8, hipMemcpyDefault));
+  } else {
+    std::vector<int32_t> t((size_t)n + 1);
+    HIP_TRY(h, hipMemcpy(t.data(), g->row_ptr, ((size_t)n + 1) * 4, hipMemcpyDefault));
+    for (size_t i = 0; i <= (size_t)n; ++i) rp[i] = t[i];
+  }
+  if (rp[0] != 0 || rp[n] != h->nnz) return set_err(h, LPA_ERR_GRAPH, "row offsets");
+  for (int v = 0; v < n; ++v)
+    if (rp[v + 1] < rp[v] || rp[v + 1] - rp[v] > (int64_t)INT32_MAX)
+      return set_err(h, LPA_ERR_GRAPH, "row offsets");
+  const int64_t kib = cfg.stream_chunk_kib > 0 ? cfg.stream_chunk_kib : 262144;
+  const int64_t chunk = kib * 1024 / 4;  // entries (4-byte column indices)
+  int64_t cap = 1;
+  for (int v0 = 0; v0 < n;) {
+    const int64_t b = rp[v0];
+    int v1 = v0 + 1;
+    if (rp[v1] - b <= chunk) {  // the largest v1 whose rows fit the chunk
+      int lo = v1, hi = n;
+      while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (rp[mid] - b <= chunk)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      v1 = lo;
+    }
+    S.first.push_back(v0);
+    S.base.push_back(b);
+    S.entries.push_back(rp[v1] - b);
+    cap = std::max(cap, rp[v1] - b);
+    v0 = v1;
+  }
+  S.first.push_back(n);
+  const size_t P = S.base.size();
+  const size_t rp_bytes = ((size_t)n + 1) * (g->row_ptr64 ? 8 : 4);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + (bytes ? bytes : 1));
+    return at;
+  };
+  const size_t o_rp = take(rp_bytes), o_order = take((size_t)n * 4),
+               o_desc = take(P * sizeof(GraphDesc)), o_pref = take(P * 2 * sizeof(int32_t));
+  constexpr int NB = lpa_handle::Streamed::kBufs;
+  size_t o_col[NB], o_w[NB] = {};
+  for (int i = 0; i < NB; ++i) {
+    o_col[i] = take((size_t)cap * 4);
+    if (S.host_w) o_w[i] = take((size_t)cap * 4);
+  }
+  if (hipMalloc(&S.dev, off) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(h, LPA_ERR_NOMEM, "hipMalloc failed (stream buffers)");
+  }
+  S.dev_bytes = off;
+  char *base = (char *)S.dev;
+  const void *rp_src = g->row_ptr64 ? (const void *)g->row_ptr64 : (const void *)g->row_ptr;
+  HIP_TRY(h, hipMemcpy(base + o_rp, rp_src, rp_bytes, hipMemcpyDefault));
+  h->row_ptr = g->row_ptr64 ? RowPtr{nullptr, (const int64_t *)(base + o_rp)}
+                            : RowPtr{(const int32_t *)(base + o_rp), nullptr};
+  S.order = (int32_t *)(base + o_order);
+  S.desc = (GraphDesc *)(base + o_desc);
+  S.prefix = (int32_t *)(base + o_pref);
+  for (int i = 0; i < NB; ++i) {
+    S.col_buf[i] = (int32_t *)(base + o_col[i]);
+    S.w_buf[i] = S.host_w ? (float *)(base + o_w[i]) : nullptr;
+  }
+  HIP_TRY(h, hipStreamCreateWithFlags(&S.copy, hipStreamNonBlocking));
+  S.cs[0] = h->stream;
+  for (int i = 1; i < NB; ++i) HIP_TRY(h, hipStreamCreateWithFlags(&S.cs[i], hipStreamNonBlocking));
+  for (int i = 0; i < NB; ++i) {
+    HIP_TRY(h, hipEventCreateWithFlags(&S.copied[i], hipEventDisableTiming));
+    HIP_TRY(h, hipEventCreateWithFlags(&S.done[i], hipEventDisableTiming));
+  }
+  HIP_TRY(h, hipEventCreateWithFlags(&S.start, hipEventDisableTiming));
+  return LPA_OK;
+}
+
+// Bin every range by degree into the second order and upload one
+// descriptor per range: the handle's own, with that range's vertices and
+// the column and weight pointers moved so that a CSR position q of the
+// range addresses its slice buffer (buffer - first position + q).
+int stream_bin(lpa_handle *h) {
+  lpa_handle::Streamed &S = h->sm;
+  const size_t P = S.base.size();
+  std::vector<GraphDesc> descs(P, h->desc);
+  std::vector<int32_t> pref(2 * P, 0);
+  S.items.assign(P, 0);
+  int64_t off = 0;
+  for (size_t p = 0; p < P; ++p) {
+    int hubs = 0, lanes = 0;
+    HIP_TRY(h, bin_range(h, S.first[p], S.first[p + 1] - S.first[p], S.order + off, &hubs,
+                         &lanes));
+    GraphDesc &d = descs[p];
+    const uintptr_t shift = (uintptr_t)S.base[p] * 4;
+    const int slot = (int)(p % lpa_handle::Streamed::kBufs);
+    d.col = (const int32_t *)((uintptr_t)S.col_buf[slot] - shift);
+    d.w = S.host_w ? (const float *)((uintptr_t)S.w_buf[slot] - shift) : nullptr;
+    d.order = S.order + off;
+    d.n_hubs = hubs;
+    d.n_lane = lanes;
+    d.n_seg = 0;
+    d.items = hubs + (lanes + kWave - 1) / kWave;
+    S.items[p] = d.items;
+    pref[2 * p + 1] = d.items;
+    off += hubs + lanes;
+  }
+  HIP_TRY(h, hipMemcpy(S.desc, descs.data(), P * sizeof(GraphDesc), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(S.prefix, pref.data(), pref.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
+  int cus = 1;
+  HIP_TRY(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+  S.grid_cap = cus * move_blocks_per_cu(kernel_k(h->k, h->flags), false,
+                                        (h->flags & LPA_RESCAN) != 0,
+                                        (h->flags & LPA_SHARED_VARS) != 0,
+                                        h->row_ptr.p64 != nullptr);
+  return LPA_OK;
+}
+
+void stream_release(lpa_handle *h) {
+  lpa_handle::Streamed &S = h->sm;
+  constexpr int NB = lpa_handle::Streamed::kBufs;
+  if (S.copy) (void)hipStreamSynchronize(S.copy);
+  for (int i = 1; i < NB; ++i)
+    if (S.cs[i]) (void)hipStreamSynchronize(S.cs[i]);
+  for (int i = 0; i < NB; ++i) {
+    if (S.copied[i]) (void)hipEventDestroy(S.copied[i]);
+    if (S.done[i]) (void)hipEventDestroy(S.done[i]);
+  }
+  if (S.start) (void)hipEventDestroy(S.start);
+  for (int i = 1; i < NB; ++i)
+    if (S.cs[i]) (void)hipStreamDestroy(S.cs[i]);
+  if (S.copy) (void)hipStreamDestroy(S.copy);
+  if (S.dev) (void)hipFree(S.dev);
+  S = lpa_handle::Streamed{};
+}
+
+// Up to `iters` iterations of a streamed graph.  Range p uses buffer and
+// compute stream p % kBufs: the copy stream fills the buffer once the kernel
+// that last read it has finished, the compute stream runs the range's move
+// kernel once the copy has landed.  The ranges of one iteration may run
+// concurrently (the synchronous update reads only the previous labels and
+// writes each vertex once; neighbour flags are set, never cleared, by the
+// move kernels); every compute stream starts after the previous stop test,
+// and the handle's stream joins them all before this iteration's.  The
+// status is read back after every iteration.
+int stream_iterate(lpa_handle *h, int iters) {
+  lpa_handle::Streamed &S = h->sm;
+  lpa_batch *b = h->self;
+  lpa_handle *one[1] = {h};
+  int rc;
+  if ((rc = batch_load(b, one, 1)) != LPA_OK) return rc;
+  const Launch L0 = make_launch(b);
+  const int kk = kernel_k(h->k, h->flags);
+  const bool rescan = (h->flags & LPA_RESCAN) != 0, sv = (h->flags & LPA_SHARED_VARS) != 0;
+  const bool wide = h->row_ptr.p64 != nullptr;
+  const int waves_per_block = kBlock / kWave;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, h->stream, b->d_finished, 1);
+  constexpr int NB = lpa_handle::Streamed::kBufs;
+  for (int i = 0; i < iters && !h->finished; ++i) {
+    const int l = h->iter;
+    const bool prof = !h->ev_beg.empty() && l < (int)h->ev_beg.size();
+    if (prof) HIP_TRY(h, hipEventRecord(h->ev_beg[l], h->stream));
+    HIP_TRY(h, hipEventRecord(S.start, h->stream));
+    for (int c = 1; c < NB; ++c) HIP_TRY(h, hipStreamWaitEvent(S.cs[c], S.start, 0));
+    for (size_t p = 0; p < S.base.size(); ++p) {
+      const int s = (int)(p % NB);
+      if (S.entries[p] > 0) {
+        HIP_TRY(h, hipStreamWaitEvent(S.copy, S.done[s], 0));
+        HIP_TRY(h, hipMemcpyAsync(S.col_buf[s], S.host_col + S.base[p], (size_t)S.entries[p] * 4,
+                                  hipMemcpyHostToDevice, S.copy));
+        if (S.host_w)
+          HIP_TRY(h, hipMemcpyAsync(S.w_buf[s], S.host_w + S.base[p], (size_t)S.entries[p] * 4,
+                                    hipMemcpyHostToDevice, S.copy));
+        HIP_TRY(h, hipEventRecord(S.copied[s], S.copy));
+        HIP_TRY(h, hipStreamWaitEvent(S.cs[s], S.copied[s], 0));
+      }
+      Launch Lp = L0;
+      Lp.d = S.desc + p;
+      Lp.prefix_items = S.prefix + 2 * p;
+      Lp.G = 1;
+      Lp.total_items = S.items[p];
+      Lp.total_hubs = Lp.total_merge = Lp.total_segs = 0;
+      int grid = (S.items[p] + waves_per_block - 1) / waves_per_block;
+      grid = std::max(1, std::min(grid, S.grid_cap));
+      HIP_TRY(h, launch_move_det(kk, rescan, sv, wide, Lp, grid, S.cs[s]));
+      HIP_TRY(h, hipEventRecord(S.done[s], S.cs[s]));
+    }
+    for (int c = 1; c < NB; ++c) HIP_TRY(h, hipStreamWaitEvent(h->stream, S.done[c], 0));
+    HIP_TRY(h, launch_finish(L0, h->stream));
+    if (prof) HIP_TRY(h, hipEventRecord(h->ev_end[l], h->stream));
+    if ((rc = batch_read_status(b)) != LPA_OK) return rc;
+  }
+  return LPA_OK;
+}
+
+}  // namespace
+
 int lpa_free(lpa_handle *h) {
   if (!h) return LPA_OK;
   (void)hipStreamSynchronize(h->stream);
   for (hipEvent_t e : h->ev_beg) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->ev_end) (void)hipEventDestroy(e);
   for (void *p : h->eval_allocs) (void)hipFree(p);
+  stream_release(h);
   if (h->owns_block && h->block) (void)hipFree(h->block);
   batch_release(h->self);
   delete h;
@@ -933,6 +1212,11 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   if (g->n > 0 && pointer_location(rp_any) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
   if (g->nnz > 0 && pointer_location(g->col_idx) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
   if (weights && g->nnz > 0 && pointer_location(weights) == LPA_PTR_UNUSABLE) return LPA_ERR_ARG;
+  const bool streamed = (cfg.flags & LPA_STREAM_CSR) != 0;
+  if (streamed && g->nnz > 0 &&
+      (pointer_location(g->col_idx) != LPA_PTR_HOST ||
+       (weights && pointer_location(weights) != LPA_PTR_HOST)))
+    return LPA_ERR_ARG;  // streaming copies from pinned host memory
 
   lpa_handle *h = new (std::nothrow) lpa_handle();
   if (!h) return LPA_ERR_NOMEM;
@@ -973,6 +1257,9 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     h->owns_block = true;
   }
   h->core_bytes = Ly.total;
+  if (streamed && n > 0) {
+    if ((rc = stream_prepare(h, g, cfg)) != LPA_OK) return bail(rc);
+  }
   char *base = (char *)h->block;
   h->st = (GraphStatus *)(base + Ly.st);
   h->hist = (uint32_t *)(base + Ly.hist);
@@ -1021,28 +1308,11 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
 
   // degree binning (once per graph)
   if (n > 0) {
-    const int nblk = (n + kBinIds - 1) / kBinIds;
-    const size_t cells = (size_t)kClasses * nblk;
-    const int nchunks = (int)((cells + kScanChunk - 1) / kScanChunk);
-    unsigned *counts = (unsigned *)d.C[0];
-    hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, h->stream, n, h->row_ptr,
-                       h->lane_max, nblk, counts);
-    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunks), dim3(256), 0, h->stream, counts, cells,
-                       (unsigned *)h->hist);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, h->stream, (unsigned *)h->hist, nchunks,
-                       counts, nblk, h->st->totals);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, h->stream,
-                       counts, cells, (const unsigned *)h->hist);
-    hipLaunchKernelGGL(k_bin_place, dim3(nblk), dim3(256), 0, h->stream, n, h->row_ptr,
-                       h->lane_max, nblk, (const unsigned *)counts, (int32_t *)d.order);
-    int totals[4] = {0, 0, 0, 0};
-    if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(totals, h->st->totals, sizeof(totals), hipMemcpyDeviceToHost, h->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(h->stream) != hipSuccess)
+    int hubs = 0, lanes = 0;
+    if (bin_range(h, 0, n, (int32_t *)d.order, &hubs, &lanes) != hipSuccess)
       return bail(LPA_ERR_HIP);
-    d.n_hubs = totals[0];
-    d.n_lane = totals[1];
+    d.n_hubs = hubs;
+    d.n_lane = lanes;
   }
   // async: split every hub into segments of lane_max entries
   if (h->async_mode && d.n_hubs > 0) {
@@ -1064,6 +1334,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   d.hub_shared = (cfg.flags & LPA_HUB_SHARED) ? 1 : 0;
   d.items = h->async_mode ? ((d.hub_shared ? 0 : d.n_seg) + d.n_lane + kWave - 1) / kWave
                           : d.n_hubs + (d.n_lane + kWave - 1) / kWave;
+  if (h->sm.on && (rc = stream_bin(h)) != LPA_OK) return bail(rc);
 
   // the batch of one that lpa_step / lpa_run use
   h->self = new (std::nothrow) lpa_batch();
@@ -1101,8 +1372,12 @@ int lpa_step(lpa_handle *h, int64_t *changed, int *done) {
   const int l = h->iter;
   lpa_batch *b = h->self;
   lpa_handle *one[1] = {h};
-  if ((rc = batch_load(b, one, 1)) != LPA_OK) return batch_error_to_handles(b, rc);
-  if ((rc = batch_iterate(b, 1, h)) != LPA_OK) return batch_error_to_handles(b, rc);
+  if (h->sm.on) {
+    if ((rc = stream_iterate(h, 1)) != LPA_OK) return batch_error_to_handles(b, rc);
+  } else {
+    if ((rc = batch_load(b, one, 1)) != LPA_OK) return batch_error_to_handles(b, rc);
+    if ((rc = batch_iterate(b, 1, h)) != LPA_OK) return batch_error_to_handles(b, rc);
+  }
   unsigned long long dn = 0;
   HIP_TRY(h, hipMemcpyAsync(&dn, h->desc.dN + l, sizeof(dn), hipMemcpyDeviceToHost, h->stream));
   if ((rc = batch_read_status(b)) != LPA_OK) return batch_error_to_handles(b, rc);
@@ -1114,7 +1389,10 @@ int lpa_step(lpa_handle *h, int64_t *changed, int *done) {
 int lpa_run(lpa_handle *h, int *iterations) {
   int rc = check_ready(h);
   if (rc) return rc;
-  if (!h->finished) {
+  if (!h->finished && h->sm.on) {
+    if ((rc = stream_iterate(h, h->max_iter - h->iter)) != LPA_OK)
+      return batch_error_to_handles(h->self, rc);
+  } else if (!h->finished) {
     lpa_batch *b = h->self;
     lpa_handle *one[1] = {h};
     if ((rc = batch_load(b, one, 1)) != LPA_OK) return batch_error_to_handles(b, rc);
@@ -1453,7 +1731,7 @@ int lpa_progress(const lpa_handle *h, int *iteration, int *finished) {
 
 int lpa_memory(const lpa_handle *h, size_t *core_bytes, size_t *eval_bytes) {
   if (!h) return LPA_ERR_ARG;
-  if (core_bytes) *core_bytes = h->core_bytes;
+  if (core_bytes) *core_bytes = h->core_bytes + h->sm.dev_bytes;
   if (eval_bytes) *eval_bytes = h->eval_bytes;
   return LPA_OK;
 }

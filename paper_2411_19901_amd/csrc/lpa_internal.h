@@ -158,6 +158,12 @@ hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared
                             bool shared_vars, bool wide, const Launch &L, int grid,
                             int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
 int move_blocks_per_cu(int k, bool async_mode, bool rescan, bool shared_vars, bool wide);
+// LPA_MODE_DET move kernel of one launch without the stop test, and the
+// stop test alone (k_finish): an iteration split over partitions of a
+// graph runs the former once per partition, then the latter.
+hipError_t launch_move_det(int k, bool rescan, bool shared_vars, bool wide, const Launch &L,
+                           int grid, hipStream_t s);
+hipError_t launch_finish(const Launch &L, hipStream_t s);
 
 // Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read
 // by one wavefront each, order[n_hubs, n_hubs + n_lane) one lane each.

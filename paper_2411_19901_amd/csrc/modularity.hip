@@ -35,23 +35,45 @@ __device__ void add_by_label(double *tot, int c, double x, bool on) {
 
 // One step of TW entries per row (TW <= T), as in the move kernel's
 // staging: adds matching weights to `in` and stages the weights for the
-// row owners' K_i sums.
+// row owners' K_i sums.  Slots are taken kModBatch at a time, column loads,
+// then weights, then labels, so that each phase's loads are in flight
+// together (slots past a row's end issue no load).
+constexpr int kModBatch = 4;
+
 template <int TW, int T>
 __device__ __forceinline__ void mod_step(const ModArgs &m, Stage<T, long long> &st, int lane, int t0,
                                          int tn, double &ki, double &in) {
+  const gptr<const int32_t> col = as_global(m.col);
+  const gptr<const float> wp = as_global(m.w);
+  const gptr<const int32_t> lab = as_global(m.lab);
+  constexpr int B = TW < kModBatch ? TW : kModBatch;
 #pragma unroll
-  for (int i = 0; i < TW; ++i) {
-    const int slot = i * kWave + lane;
-    const int r = slot / TW, j = slot % TW;
-    const int p = t0 + j;
-    float x = 0.0f;
-    if (p < st.len[r]) {
-      const long long e = st.beg[r] + p;
-      const int c = __builtin_nontemporal_load(m.col + e);
-      x = m.w ? __builtin_nontemporal_load(m.w + e) : 1.0f;
-      if (m.lab[c] == st.self[r]) in += (double)x;
+  for (int i0 = 0; i0 < TW; i0 += B) {
+    bool ok[B];
+    int c[B], l[B];
+    float x[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int slot = (i0 + b) * kWave + lane;
+      const int r = slot / TW, j = slot % TW;
+      ok[b] = t0 + j < st.len[r];
+      c[b] = ok[b] ? __builtin_nontemporal_load(col + (st.beg[r] + (t0 + j))) : -1;
     }
-    st.w[r * (TW + 1) + j] = x;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int slot = (i0 + b) * kWave + lane;
+      const int r = slot / TW, j = slot % TW;
+      x[b] = !ok[b] ? 0.0f : (wp ? __builtin_nontemporal_load(wp + (st.beg[r] + (t0 + j))) : 1.0f);
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) l[b] = ok[b] ? lab[c[b]] : -1;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int slot = (i0 + b) * kWave + lane;
+      const int r = slot / TW, j = slot % TW;
+      if (ok[b] && l[b] == st.self[r]) in += (double)x[b];
+      st.w[r * (TW + 1) + j] = x[b];
+    }
   }
   wave_lds_sync();
   if (m.w) {
@@ -103,7 +125,10 @@ __device__ void mod_lane_rows(const ModArgs &m, Stage<T, long long> &st, int lan
 __device__ void mod_hub(const ModArgs &m, int v, double &k_acc, double &in_acc, int &pc,
                         double &ps) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int ci = m.lab[v];
+  const gptr<const int32_t> col = as_global(m.col);
+  const gptr<const float> wp = as_global(m.w);
+  const gptr<const int32_t> lab = as_global(m.lab);
+  const int ci = lab[v];
   const long long rb = m.row_ptr[v], re = m.row_ptr[v + 1];
   constexpr int U = 4;
   double ki = 0.0, in = 0.0;
@@ -113,16 +138,16 @@ __device__ void mod_hub(const ModArgs &m, int v, double &k_acc, double &in_acc, 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const long long e = e0 + u * kWave + lane;
-      c[u] = -1;
-      x[u] = 0.0f;
-      if (e < re) {
-        c[u] = __builtin_nontemporal_load(m.col + e);
-        x[u] = m.w ? __builtin_nontemporal_load(m.w + e) : 1.0f;
-      }
+      c[u] = e < re ? __builtin_nontemporal_load(col + e) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long e = e0 + u * kWave + lane;
+      x[u] = e >= re ? 0.0f : (wp ? __builtin_nontemporal_load(wp + e) : 1.0f);
     }
     int l[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) l[u] = c[u] >= 0 ? m.lab[c[u]] : -1;
+    for (int u = 0; u < U; ++u) l[u] = c[u] >= 0 ? lab[c[u]] : -1;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ki += (double)x[u];

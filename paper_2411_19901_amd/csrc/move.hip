@@ -287,16 +287,41 @@ struct Rescan {
 __device__ __forceinline__ void mark(const MoveArgs &a, int j) { a.act_next[j] = 1; }
 
 // Mark the neighbours of every lane whose `moved` is set (entries [beg, beg +
-// len) of its row), with row-contiguous column loads by the whole wavefront.
+// len) of its row), with row-contiguous column loads by the whole wavefront:
+// all of a step's column loads are issued before its flag stores.
 template <int TW, int T, class Pos>
 __device__ __forceinline__ void mark_step(const MoveArgs &a, const Stage<T, Pos> &st, int lane,
                                           int t0) {
+  bool ok[TW];
+  int c[TW];
 #pragma unroll
   for (int i = 0; i < TW; ++i) {
     const int slot = i * kWave + lane;
     const int r = slot / TW, j = slot % TW;
-    const int p = t0 + j;
-    if (p < st.len[r]) mark(a, __builtin_nontemporal_load(a.col + st.beg[r] + p));
+    ok[i] = t0 + j < st.len[r];
+    c[i] = ok[i] ? __builtin_nontemporal_load(a.col + (st.beg[r] + (t0 + j))) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < TW; ++i)
+    if (ok[i]) mark(a, c[i]);
+}
+
+// Mark the neighbours of entries [beg, end) of one row, the whole wavefront
+// taking 64 x kMarkUnroll entries at a time (loads first, then stores).
+constexpr int kMarkUnroll = 4;
+
+template <class Pos>
+__device__ __forceinline__ void mark_row(const MoveArgs &a, Pos beg, Pos end, int lane) {
+  for (Pos q0 = beg; q0 < end; q0 += kMarkUnroll * kWave) {
+    int c[kMarkUnroll];
+#pragma unroll
+    for (int u = 0; u < kMarkUnroll; ++u) {
+      const Pos q = q0 + u * kWave + lane;
+      c[u] = q < end ? __builtin_nontemporal_load(a.col + q) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kMarkUnroll; ++u)
+      if (c[u] >= 0) mark(a, c[u]);
   }
 }
 
@@ -489,7 +514,7 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
   if (lane == 0) a.Cn[v] = moved ? c : cv;
   if (moved) {
     changed += 1;
-    for (Pos q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
+    mark_row(a, beg, end, lane);
   }
   scanned += (unsigned long long)(end - beg);
 }
@@ -578,7 +603,7 @@ __device__ void hub_vertex_det_sv(const MoveArgs &a, int v, unsigned long long &
   if (lane == 0) a.Cn[v] = moved ? bk : cv;
   if (moved) {
     changed += 1;
-    for (Pos q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
+    mark_row(a, beg, end, lane);
   }
   scanned += (unsigned long long)(end - beg);
 }
@@ -607,7 +632,7 @@ __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &
   if (lane == 0) a.Cn[v] = moved ? c : cv;
   if (moved) {
     changed += 1;
-    for (Pos q = beg + lane; q < end; q += kWave) mark(a, __builtin_nontemporal_load(a.col + q));
+    mark_row(a, beg, end, lane);
   }
   scanned += (unsigned long long)(end - beg);
 }
@@ -1157,8 +1182,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_mark(Launch L) {
     const int q = u - a.hub_pbase[h];
     const long long rb = a.row_ptr[v], re = a.row_ptr[v + 1];
     const long long beg = rb + (long long)q * a.seg_len, end = min(beg + a.seg_len, re);
-    for (long long e = beg + lane; e < end; e += kWave)
-      mark(a, __builtin_nontemporal_load(a.col + e));
+    mark_row(a, beg, end, lane);
   }
 }
 
@@ -1437,6 +1461,53 @@ static int move_blocks_w(int k, bool async_mode, bool rescan, bool shared_vars) 
   if (k == 0) return async_mode ? occ_t<0, true, false, W>() : occ_t<0, false, false, W>();
   if (rescan) return async_mode ? occ_mode<true, true, W>(k) : occ_mode<false, true, W>(k);
   return async_mode ? occ_mode<true, false, W>(k) : occ_mode<false, false, W>(k);
+}
+
+// LPA_MODE_DET move kernel alone, for launches that split one iteration
+// over several partitions of a graph (the stop test follows separately).
+template <int K, bool W>
+static hipError_t launch_move_det_t(bool rescan, bool shared_vars, const Launch &L, int grid,
+                                    hipStream_t s) {
+  if (L.total_items <= 0) return hipSuccess;
+  if constexpr (K > 0) {
+    if (rescan)
+      hipLaunchKernelGGL((k_move_rescan<K, false, W>), dim3(grid), dim3(kBlock), 0, s, L);
+    else if (shared_vars)
+      hipLaunchKernelGGL((k_move_sv<K, W>), dim3(grid), dim3(kBlock), 0, s, L);
+    else
+      hipLaunchKernelGGL((k_move<K, false, W>), dim3(grid), dim3(kBlock), 0, s, L);
+  } else {
+    if (rescan || shared_vars) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_move<0, false, W>), dim3(grid), dim3(kBlock), 0, s, L);
+  }
+  return hipGetLastError();
+}
+
+template <bool W>
+static hipError_t launch_move_det_w(int k, bool rescan, bool shared_vars, const Launch &L,
+                                    int grid, hipStream_t s) {
+  switch (k) {
+    case 0: return launch_move_det_t<0, W>(rescan, shared_vars, L, grid, s);
+    case 1: return launch_move_det_t<1, W>(rescan, shared_vars, L, grid, s);
+    case 2: return launch_move_det_t<2, W>(rescan, shared_vars, L, grid, s);
+    case 4: return launch_move_det_t<4, W>(rescan, shared_vars, L, grid, s);
+    case 8: return launch_move_det_t<8, W>(rescan, shared_vars, L, grid, s);
+    case 16: return launch_move_det_t<16, W>(rescan, shared_vars, L, grid, s);
+    case 32: return launch_move_det_t<32, W>(rescan, shared_vars, L, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_move_det(int k, bool rescan, bool shared_vars, bool wide, const Launch &L,
+                           int grid, hipStream_t s) {
+  return wide ? launch_move_det_w<true>(k, rescan, shared_vars, L, grid, s)
+              : launch_move_det_w<false>(k, rescan, shared_vars, L, grid, s);
+}
+
+hipError_t launch_finish(const Launch &L, hipStream_t s) {
+  const int fg = (L.G + 255) / 256 < 64 ? (L.G + 255) / 256 : 64;
+  hipLaunchKernelGGL(k_finish, dim3(fg > 0 ? fg : 1), dim3(256), 0, s, L);
+  return hipGetLastError();
 }
 
 int move_blocks_per_cu(int k, bool async_mode, bool rescan, bool shared_vars, bool wide) {

@@ -37,6 +37,7 @@ LPA_RESCAN = 0x400
 LPA_HUB_SHARED = 0x800
 LPA_CAPTURE = 0x1000
 LPA_SHARED_VARS = 0x2000
+LPA_STREAM_CSR = 0x4000
 
 MODES = {"det": LPA_MODE_DET, "async": LPA_MODE_ASYNC}
 # per-vertex rule: the k-slot weighted Misra-Gries sketch, or the
@@ -54,7 +55,8 @@ class LpaConfig(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("rho", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("lane_max_degree", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t), ("reserved", ctypes.c_int32 * 4)]
+                ("workspace_bytes", ctypes.c_size_t), ("stream_chunk_kib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class LpaError(RuntimeError):
@@ -316,7 +318,8 @@ class LPA:
                  max_iter: int = 20, seed: int = 0, mode: str = "det", rho: int = 8,
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
                  stream=None, workspace=None, rule: str = "mg", rescan: bool = False,
-                 hub_shared: bool = False, capture: bool = False, shared_vars: bool = False):
+                 hub_shared: bool = False, capture: bool = False, shared_vars: bool = False,
+                 stream_csr: bool = False, stream_chunk_kib: int = 0):
         import torch
 
         def usable(t):  # device memory, or pinned host memory the device maps
@@ -339,7 +342,8 @@ class LPA:
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
                      | (LPA_RESCAN if rescan else 0) | (LPA_HUB_SHARED if hub_shared else 0)
                      | (LPA_SHARED_VARS if shared_vars else 0)
-                     | (LPA_CAPTURE if capture else 0))
+                     | (LPA_CAPTURE if capture else 0) | (LPA_STREAM_CSR if stream_csr else 0))
+        cfg.stream_chunk_kib = stream_chunk_kib
         cfg.rho = rho
         if stream is None:
             stream = torch.cuda.current_stream(self.device)

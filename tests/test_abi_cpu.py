@@ -29,7 +29,7 @@ def test_config_default():
     assert cfg.flags == lpa.LPA_MODE_DET | lpa.LPA_VALIDATE
     assert cfg.rho == 8 and not cfg.stream and cfg.lane_max_degree == 0
     assert cfg.check_every == 0 and not cfg.workspace and cfg.workspace_bytes == 0
-    assert list(cfg.reserved) == [0] * 4
+    assert cfg.stream_chunk_kib == 0 and list(cfg.reserved) == [0] * 3
 
 
 def _init(**kw):
@@ -108,7 +108,7 @@ def test_bm_paper_rule_flag():
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
     assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
-    cfg.flags = lpa.LPA_MODE_DET | 0x4000
+    cfg.flags = lpa.LPA_MODE_DET | 0x8000
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_UNSUPPORTED
     # shared variables instead of votes: det sketch rule without double scan only
@@ -161,3 +161,26 @@ def test_offsets64_workspace_bounds():
     cfg.flags = lpa.LPA_MODE_DET  # no segments in det mode
     assert L.lpa_workspace_bytes(1 << 25, 1 << 31, 8, 20, ctypes.byref(cfg),
                                  ctypes.byref(out)) == lpa.LPA_OK
+
+
+def test_stream_csr_config():
+    """Streaming needs det mode; the chunk size and the reserved words are
+    checked before any device work."""
+    L = lpa.load()
+    out = ctypes.c_size_t(0)
+    cfg = lpa.lpa_config_default()
+    cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_STREAM_CSR
+    cfg.stream_chunk_kib = 64
+    assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+        lpa.LPA_OK
+    cfg.flags = lpa.LPA_MODE_ASYNC | lpa.LPA_STREAM_CSR
+    assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+        lpa.LPA_ERR_ARG
+    cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_STREAM_CSR
+    cfg.stream_chunk_kib = -1
+    assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+        lpa.LPA_ERR_ARG
+    cfg.stream_chunk_kib = 0
+    cfg.reserved[0] = 1
+    assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+        lpa.LPA_ERR_ARG
