@@ -121,20 +121,23 @@ typedef enum lpa_status {
  * and atomic minimums (the shared-variable protocol of Algorithm 5) instead
  * of wavefront votes.  Results are identical; only the speed differs. */
 #define LPA_SHARED_VARS 0x2000u
-/* Stream the graph from host memory (LPA_MODE_DET; LPA_ERR_ARG otherwise):
+/* Stream the graph from host memory (not with LPA_HUB_SHARED: LPA_ERR_ARG):
  * col_idx and the weights must be pinned host memory (LPA_PTR_HOST; the
  * row offsets may be host or device memory and are copied to the device
  * once).  lpa_init cuts the vertices into consecutive id ranges whose rows
  * fill at most stream_chunk_kib KiB of column indices (a range is one
- * vertex when that vertex alone is larger) and bins each range by degree.
+ * vertex when that vertex alone is larger) and bins each range by degree
+ * (LPA_MODE_ASYNC: and splits each range's hubs into segments of their own).
  * Every iteration then copies the ranges' rows into four device buffers in
  * turn with DMA on a stream of the handle's own; each range's move kernel
  * starts once its copy has landed, on one of four compute streams (the
  * caller's and three of the handle's), so copies and up to four ranges'
- * kernels overlap.  The synchronous update makes the labels independent of
- * the cut and of that overlap: results are identical to the unstreamed
- * run.  Device memory: the library state, a second degree order (4 B per
- * vertex), the row offsets and the four buffers; not the graph.  lpa_run checks convergence after every
+ * kernels overlap.  In LPA_MODE_DET the synchronous update makes the
+ * labels independent of the cut and of that overlap: results are identical
+ * to the unstreamed run; LPA_MODE_ASYNC runs the ranges in place like its
+ * wavefronts.  Device memory: the library state, a second degree order (4 B
+ * per vertex), the row offsets, each range's hub segments (async) and the
+ * four buffers; not the graph.  lpa_run checks convergence after every
  * iteration; LPA_CAPTURE and lpa_batch_* do not apply (batches refuse such
  * handles with LPA_ERR_ARG). */
 #define LPA_STREAM_CSR 0x4000u

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <new>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -432,8 +433,12 @@ struct lpa_handle {
     int32_t *order = nullptr;            // device [n]: vertices of each range by degree
     std::vector<int32_t> items;          // per range: move work items
     GraphDesc *desc = nullptr;           // device [ranges]
-    int32_t *prefix = nullptr;           // device [ranges][2] = {0, items}
-    int grid_cap = 1;
+    int32_t *prefix = nullptr;  // device [ranges][8]: {0, items, 0, hubs, 0, merge items, 0, segments}
+    // LPA_MODE_ASYNC: each range's hub segments (bounds from its entries)
+    std::vector<int32_t> hub_cap, seg_cap, hubs, segs;
+    std::vector<std::array<size_t, 6>> o_hub;  // offsets in dev: pbase, flags, segment hubs,
+                                               // partial keys, partial values, candidates
+    int grid_cap = 1, cus = 1;
   } sm;
 };
 
@@ -523,7 +528,7 @@ int check_k(int k, uint32_t flags) {
   if ((flags & LPA_SHARED_VARS) &&
       ((flags & LPA_MODE_MASK) != LPA_MODE_DET || (flags & (LPA_RULE_BM_PAPER | LPA_RESCAN))))
     return LPA_ERR_ARG;
-  if ((flags & LPA_STREAM_CSR) && (flags & LPA_MODE_MASK) != LPA_MODE_DET) return LPA_ERR_ARG;
+  if ((flags & LPA_STREAM_CSR) && (flags & LPA_HUB_SHARED)) return LPA_ERR_ARG;
   return LPA_OK;
 }
 
@@ -751,6 +756,7 @@ Launch make_launch(lpa_batch *b) {
   L.total_segs = b->total_segs;
   L.finished = b->d_finished;
   L.status_out = b->d_status;
+  L.no_finish = 0;
   return L;
 }
 
@@ -1019,7 +1025,25 @@ int stream_prepare(lpa_handle *h, const lpa_graph *g, const lpa_config &cfg) {
     return at;
   };
   const size_t o_rp = take(rp_bytes), o_order = take((size_t)n * 4),
-               o_desc = take(P * sizeof(GraphDesc)), o_pref = take(P * 2 * sizeof(int32_t));
+               o_desc = take(P * sizeof(GraphDesc)), o_pref = take(P * 8 * sizeof(int32_t));
+  if (h->async_mode) {  // per range: pbase, hub flags, segment hubs, partials, candidates
+    const int64_t Sd = h->lane_max, k = h->k;
+    for (size_t p = 0; p < P; ++p) {
+      const int64_t nv = S.first[p + 1] - S.first[p];
+      const int32_t hc = (int32_t)std::min<int64_t>(S.entries[p] / (Sd + 1) + 1, nv);
+      const int32_t sc = (int32_t)(2 * (S.entries[p] / Sd) + 2);
+      S.hub_cap.push_back(hc);
+      S.seg_cap.push_back(sc);
+      std::array<size_t, 6> o;
+      o[0] = take(((size_t)hc + 1) * 4);
+      o[1] = take((size_t)hc);
+      o[2] = take((size_t)sc * 4);
+      o[3] = take((size_t)sc * k * 4);
+      o[4] = take((size_t)sc * k * 4);
+      o[5] = take((size_t)hc * k * 4);
+      S.o_hub.push_back(o);
+    }
+  }
   constexpr int NB = lpa_handle::Streamed::kBufs;
   size_t o_col[NB], o_w[NB] = {};
   for (int i = 0; i < NB; ++i) {
@@ -1062,25 +1086,59 @@ int stream_bin(lpa_handle *h) {
   lpa_handle::Streamed &S = h->sm;
   const size_t P = S.base.size();
   std::vector<GraphDesc> descs(P, h->desc);
-  std::vector<int32_t> pref(2 * P, 0);
+  std::vector<int32_t> pref(8 * P, 0);
   S.items.assign(P, 0);
+  S.hubs.assign(P, 0);
+  S.segs.assign(P, 0);
+  char *dev = (char *)S.dev;
   int64_t off = 0;
   for (size_t p = 0; p < P; ++p) {
     int hubs = 0, lanes = 0;
     HIP_TRY(h, bin_range(h, S.first[p], S.first[p + 1] - S.first[p], S.order + off, &hubs,
                          &lanes));
     GraphDesc &d = descs[p];
-    const uintptr_t shift = (uintptr_t)S.base[p] * 4;
     const int slot = (int)(p % lpa_handle::Streamed::kBufs);
+    const uintptr_t shift = (uintptr_t)S.base[p] * 4;
     d.col = (const int32_t *)((uintptr_t)S.col_buf[slot] - shift);
     d.w = S.host_w ? (const float *)((uintptr_t)S.w_buf[slot] - shift) : nullptr;
     d.order = S.order + off;
     d.n_hubs = hubs;
     d.n_lane = lanes;
     d.n_seg = 0;
-    d.items = hubs + (lanes + kWave - 1) / kWave;
+    int nseg = 0;
+    if (h->async_mode) {  // this range's hubs split into segments of lane_max entries
+      const std::array<size_t, 6> &o = S.o_hub[p];
+      d.hub_pbase = (const int32_t *)(dev + o[0]);
+      d.hub_act = (uint8_t *)(dev + o[1]);
+      d.seg_hub = (const int32_t *)(dev + o[2]);
+      d.part_key = (int32_t *)(dev + o[3]);
+      d.part_val = (float *)(dev + o[4]);
+      d.hub_cand = (int32_t *)(dev + o[5]);
+      if (hubs > S.hub_cap[p]) return set_err(h, LPA_ERR_GRAPH, "hub bound violated");
+      if (hubs > 0) {
+        hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(1024), 0, h->stream, d.order, hubs,
+                           h->row_ptr, h->lane_max, (int32_t *)d.hub_pbase, &h->st->totals[2]);
+        HIP_TRY(h, hipGetLastError());
+        HIP_TRY(h, hipMemcpyAsync(&nseg, &h->st->totals[2], sizeof(int), hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        if (nseg > S.seg_cap[p]) return set_err(h, LPA_ERR_GRAPH, "segment bound violated");
+        hipLaunchKernelGGL(k_fill_seg_hub, dim3(grid_for(hubs)), dim3(kAuxBlock), 0, h->stream,
+                           d.hub_pbase, hubs, (int32_t *)d.seg_hub);
+        HIP_TRY(h, hipGetLastError());
+      }
+      d.n_seg = nseg;
+      d.items = (nseg + lanes + kWave - 1) / kWave;
+    } else {
+      d.items = hubs + (lanes + kWave - 1) / kWave;
+    }
     S.items[p] = d.items;
-    pref[2 * p + 1] = d.items;
+    S.hubs[p] = hubs;
+    S.segs[p] = nseg;
+    pref[8 * p + 1] = d.items;
+    pref[8 * p + 3] = h->async_mode ? hubs : 0;
+    pref[8 * p + 5] = h->async_mode ? (hubs + kMergeHubs - 1) / kMergeHubs : 0;
+    pref[8 * p + 7] = nseg;
     off += hubs + lanes;
   }
   HIP_TRY(h, hipMemcpy(S.desc, descs.data(), P * sizeof(GraphDesc), hipMemcpyHostToDevice));
@@ -1088,7 +1146,8 @@ int stream_bin(lpa_handle *h) {
                        hipMemcpyHostToDevice));
   int cus = 1;
   HIP_TRY(h, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-  S.grid_cap = cus * move_blocks_per_cu(kernel_k(h->k, h->flags), false,
+  S.cus = cus;
+  S.grid_cap = cus * move_blocks_per_cu(kernel_k(h->k, h->flags), h->async_mode,
                                         (h->flags & LPA_RESCAN) != 0,
                                         (h->flags & LPA_SHARED_VARS) != 0,
                                         h->row_ptr.p64 != nullptr);
@@ -1155,13 +1214,22 @@ int stream_iterate(lpa_handle *h, int iters) {
       }
       Launch Lp = L0;
       Lp.d = S.desc + p;
-      Lp.prefix_items = S.prefix + 2 * p;
+      Lp.prefix_items = S.prefix + 8 * p;
+      Lp.prefix_hubs = S.prefix + 8 * p + 2;
+      Lp.prefix_merge = S.prefix + 8 * p + 4;
+      Lp.prefix_segs = S.prefix + 8 * p + 6;
       Lp.G = 1;
       Lp.total_items = S.items[p];
-      Lp.total_hubs = Lp.total_merge = Lp.total_segs = 0;
+      Lp.total_hubs = h->async_mode ? S.hubs[p] : 0;
+      Lp.total_merge = h->async_mode ? (S.hubs[p] + kMergeHubs - 1) / kMergeHubs : 0;
+      Lp.total_segs = S.segs[p];
+      Lp.no_finish = 1;
       int grid = (S.items[p] + waves_per_block - 1) / waves_per_block;
       grid = std::max(1, std::min(grid, S.grid_cap));
-      HIP_TRY(h, launch_move_det(kk, rescan, sv, wide, Lp, grid, S.cs[s]));
+      int mg = (Lp.total_merge + waves_per_block - 1) / waves_per_block;
+      mg = std::max(1, std::min(mg, S.cus * 4));
+      HIP_TRY(h, launch_iteration(kk, h->async_mode, rescan, false, sv, wide, Lp, grid, mg,
+                                  S.cs[s], nullptr, nullptr));
       HIP_TRY(h, hipEventRecord(S.done[s], S.cs[s]));
     }
     for (int c = 1; c < NB; ++c) HIP_TRY(h, hipStreamWaitEvent(h->stream, S.done[c], 0));

@@ -116,6 +116,7 @@ struct Launch {
   int32_t total_segs;
   int32_t *finished;        // graphs that have finished (counter)
   int32_t *status_out;      // [2 * G]: iter, done of every graph after the launch
+  int32_t no_finish;        // 1: launch_iteration leaves out the stop test (k_finish)
 };
 
 // Per-graph view used by the move kernels for one iteration.
@@ -158,11 +159,9 @@ hipError_t launch_iteration(int k, bool async_mode, bool rescan, bool hub_shared
                             bool shared_vars, bool wide, const Launch &L, int grid,
                             int merge_grid, hipStream_t s, hipEvent_t ev_beg, hipEvent_t ev_end);
 int move_blocks_per_cu(int k, bool async_mode, bool rescan, bool shared_vars, bool wide);
-// LPA_MODE_DET move kernel of one launch without the stop test, and the
-// stop test alone (k_finish): an iteration split over partitions of a
-// graph runs the former once per partition, then the latter.
-hipError_t launch_move_det(int k, bool rescan, bool shared_vars, bool wide, const Launch &L,
-                           int grid, hipStream_t s);
+// The stop test alone (k_finish): an iteration split over id ranges of a
+// graph runs launch_iteration once per range with Launch::no_finish set,
+// then this once.
 hipError_t launch_finish(const Launch &L, hipStream_t s);
 
 // Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read

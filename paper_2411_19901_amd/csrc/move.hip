@@ -1335,8 +1335,10 @@ static hipError_t launch_t(const Launch &L, int grid, int merge_grid, hipStream_
     }
     if (L.total_segs > 0) hipLaunchKernelGGL(k_hub_mark, dim3(grid), dim3(kBlock), 0, s, L);
   }
-  const int fg = (L.G + 255) / 256 < 64 ? (L.G + 255) / 256 : 64;
-  hipLaunchKernelGGL(k_finish, dim3(fg > 0 ? fg : 1), dim3(256), 0, s, L);
+  if (!L.no_finish) {
+    const int fg = (L.G + 255) / 256 < 64 ? (L.G + 255) / 256 : 64;
+    hipLaunchKernelGGL(k_finish, dim3(fg > 0 ? fg : 1), dim3(256), 0, s, L);
+  }
   return hipGetLastError();
 }
 
@@ -1461,47 +1463,6 @@ static int move_blocks_w(int k, bool async_mode, bool rescan, bool shared_vars) 
   if (k == 0) return async_mode ? occ_t<0, true, false, W>() : occ_t<0, false, false, W>();
   if (rescan) return async_mode ? occ_mode<true, true, W>(k) : occ_mode<false, true, W>(k);
   return async_mode ? occ_mode<true, false, W>(k) : occ_mode<false, false, W>(k);
-}
-
-// LPA_MODE_DET move kernel alone, for launches that split one iteration
-// over several partitions of a graph (the stop test follows separately).
-template <int K, bool W>
-static hipError_t launch_move_det_t(bool rescan, bool shared_vars, const Launch &L, int grid,
-                                    hipStream_t s) {
-  if (L.total_items <= 0) return hipSuccess;
-  if constexpr (K > 0) {
-    if (rescan)
-      hipLaunchKernelGGL((k_move_rescan<K, false, W>), dim3(grid), dim3(kBlock), 0, s, L);
-    else if (shared_vars)
-      hipLaunchKernelGGL((k_move_sv<K, W>), dim3(grid), dim3(kBlock), 0, s, L);
-    else
-      hipLaunchKernelGGL((k_move<K, false, W>), dim3(grid), dim3(kBlock), 0, s, L);
-  } else {
-    if (rescan || shared_vars) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_move<0, false, W>), dim3(grid), dim3(kBlock), 0, s, L);
-  }
-  return hipGetLastError();
-}
-
-template <bool W>
-static hipError_t launch_move_det_w(int k, bool rescan, bool shared_vars, const Launch &L,
-                                    int grid, hipStream_t s) {
-  switch (k) {
-    case 0: return launch_move_det_t<0, W>(rescan, shared_vars, L, grid, s);
-    case 1: return launch_move_det_t<1, W>(rescan, shared_vars, L, grid, s);
-    case 2: return launch_move_det_t<2, W>(rescan, shared_vars, L, grid, s);
-    case 4: return launch_move_det_t<4, W>(rescan, shared_vars, L, grid, s);
-    case 8: return launch_move_det_t<8, W>(rescan, shared_vars, L, grid, s);
-    case 16: return launch_move_det_t<16, W>(rescan, shared_vars, L, grid, s);
-    case 32: return launch_move_det_t<32, W>(rescan, shared_vars, L, grid, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_move_det(int k, bool rescan, bool shared_vars, bool wide, const Launch &L,
-                           int grid, hipStream_t s) {
-  return wide ? launch_move_det_w<true>(k, rescan, shared_vars, L, grid, s)
-              : launch_move_det_w<false>(k, rescan, shared_vars, L, grid, s);
 }
 
 hipError_t launch_finish(const Launch &L, hipStream_t s) {

@@ -164,8 +164,8 @@ def test_offsets64_workspace_bounds():
 
 
 def test_stream_csr_config():
-    """Streaming needs det mode; the chunk size and the reserved words are
-    checked before any device work."""
+    """Streaming excludes the shared hub sketch; the chunk size and the
+    reserved words are checked before any device work."""
     L = lpa.load()
     out = ctypes.c_size_t(0)
     cfg = lpa.lpa_config_default()
@@ -174,6 +174,9 @@ def test_stream_csr_config():
     assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_OK
     cfg.flags = lpa.LPA_MODE_ASYNC | lpa.LPA_STREAM_CSR
+    assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
+        lpa.LPA_OK
+    cfg.flags = lpa.LPA_MODE_ASYNC | lpa.LPA_STREAM_CSR | lpa.LPA_HUB_SHARED
     assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_ARG
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_STREAM_CSR

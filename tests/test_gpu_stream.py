@@ -1,12 +1,15 @@
-"""Streaming a graph from pinned host memory (LPA_STREAM_CSR, det mode).
+"""Streaming a graph from pinned host memory (LPA_STREAM_CSR).
 
-The rows are copied to the device range by range every iteration; since
-the synchronous update reads only the previous iteration's labels, the
-result must equal the oracle bit for bit whatever the cut: labels,
+The rows are copied to the device range by range every iteration.  In det
+mode the synchronous update reads only the previous iteration's labels, so
+the result must equal the oracle bit for bit whatever the cut: labels,
 iteration count, changed and scanned counts, modularity.  Chunks from
 1 KiB (256 entries, so a star's centre is a range of its own and the
 buffers grow to hold it) to one range for the whole graph; every rule and
-option of det mode; int64 offsets; rejections.
+option of det mode; int64 offsets; rejections.  Async mode (each range with
+its own hub segments): valid labels, every entry scanned in the first
+iteration, modularity equal to the oracle's of the same labels and quality
+on the planted partition.
 """
 import numpy as np
 import pytest
@@ -111,8 +114,8 @@ def test_stream_rejections():
     need_gpu()
     g = graph("sbm1-s1")
     rp, col, w = pinned(g)
-    with pytest.raises(lpa.LpaError) as ei:  # async is not streamed
-        lpa.LPA(rp, col, w, k=8, mode="async", stream_csr=True)
+    with pytest.raises(lpa.LpaError) as ei:  # no shared hub sketch when streaming
+        lpa.LPA(rp, col, w, k=8, mode="async", stream_csr=True, hub_shared=True)
     assert ei.value.code == lpa.LPA_ERR_ARG
     with pytest.raises(lpa.LpaError) as ei:  # rows must be in pinned host memory
         lpa.LPA(rp, col.cuda(), w, k=8, mode="det", stream_csr=True)
@@ -123,3 +126,26 @@ def test_stream_rejections():
         batch.run([s])
     batch.close()
     s.close()
+
+
+@pytest.mark.parametrize("chunk_kib", [1, 16, 0])
+@pytest.mark.parametrize("variant", [dict(k=8), dict(k=8, lane_max_degree=64),
+                                     dict(k=1, rule="bm_paper"), dict(k=8, rescan=True)])
+def test_stream_async(chunk_kib, variant):
+    need_gpu()
+    for name in ("sbm1-s1", "rmat14-w", "star5000"):
+        g = graph(name)
+        rp, col, w = pinned(g)
+        s = lpa.LPA(rp, col, w, mode="async", stream_csr=True, stream_chunk_kib=chunk_kib,
+                    **variant)
+        it = s.run()
+        lab = s.labels(device=False)
+        assert 1 <= it <= 20 and lab.min() >= 0 and lab.max() < g.n
+        assert s.trace()[1][0] == g.nnz  # every entry scanned in the first iteration
+        q = s.modularity()
+        assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, lab)) <= 1e-9
+        if name == "sbm1-s1" and variant.get("rule") != "bm_paper":
+            q_exact = oracle.modularity(g.row_ptr, g.col, None,
+                                        oracle.lpa_run(g.row_ptr, g.col, None, k=0)[0])
+            assert q > 0.9 * q_exact, (q, q_exact)
+        s.close()
