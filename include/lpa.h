@@ -176,8 +176,12 @@ typedef struct lpa_config {
                               graphs exit on the device), synchronise once */
   void *workspace;         /* optional device memory for every array of the
                               handle (256-byte aligned, at least
-                              lpa_workspace_bytes); NULL = lpa_init allocates
-                              one block itself.  Borrowed like the graph. */
+                              lpa_workspace_bytes, which covers the largest
+                              possible number of async hub segments); NULL =
+                              lpa_init allocates one block itself and, in
+                              LPA_MODE_ASYNC, the partial sketches of the
+                              segments it planned in a second one.  Borrowed
+                              like the graph. */
   size_t workspace_bytes;
   int32_t stream_chunk_kib; /* LPA_STREAM_CSR: rows copied per slice, in
                               KiB of column indices (the weights double

@@ -394,6 +394,7 @@ struct lpa_handle {
 
   void *block = nullptr;  // every device array of the handle
   bool owns_block = false;
+  void *part_block = nullptr;  // async partial sketches, sized once the segments are planned
   GraphDesc desc{};       // host copy of the static descriptor
   GraphStatus *st = nullptr;
   uint32_t *hist = nullptr;  // binning scratch
@@ -560,7 +561,11 @@ struct Layout {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode, int lane_max) {
+// bound_partials: reserve the partial sketches for the largest possible
+// number of hub segments (a caller workspace); otherwise lpa_init sizes them
+// once the segments are planned.
+Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode, int lane_max,
+                   bool rescan, bool bound_partials) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -597,9 +602,9 @@ Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode,
     L.hub_pbase = take(((size_t)L.hub_cap + 1) * 4);
     L.hub_act = take((size_t)L.hub_cap);
     L.seg_hub = take((size_t)L.seg_cap * 4);
-    L.pkey = take((size_t)L.seg_cap * k * 4);
-    L.pval = take((size_t)L.seg_cap * k * 4);
-    L.hcand = take((size_t)L.hub_cap * k * 4);
+    L.pkey = take(bound_partials ? (size_t)L.seg_cap * k * 4 : 0);
+    L.pval = take(bound_partials ? (size_t)L.seg_cap * k * 4 : 0);
+    L.hcand = take(rescan ? (size_t)L.hub_cap * k * 4 : 0);  // double-scan candidates
   }
   L.total = off;
   return L;
@@ -927,7 +932,8 @@ int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter, const lpa_c
   if ((rc = check_k(k, cfg.flags)) != LPA_OK) return rc;
   const bool async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   const int lane_max = cfg.lane_max_degree > 0 ? cfg.lane_max_degree : default_lane_max(async_mode);
-  const Layout Ly = plan_layout(n, nnz, k, max_iter, async_mode, lane_max);
+  const Layout Ly = plan_layout(n, nnz, k, max_iter, async_mode, lane_max,
+                                (cfg.flags & LPA_RESCAN) != 0, true);
   if (Ly.too_many_segs) return LPA_ERR_UNSUPPORTED;
   *bytes = Ly.total;
   return LPA_OK;
@@ -1249,6 +1255,7 @@ int lpa_free(lpa_handle *h) {
   for (hipEvent_t e : h->ev_end) (void)hipEventDestroy(e);
   for (void *p : h->eval_allocs) (void)hipFree(p);
   stream_release(h);
+  if (h->part_block) (void)hipFree(h->part_block);
   if (h->owns_block && h->block) (void)hipFree(h->block);
   batch_release(h->self);
   delete h;
@@ -1311,7 +1318,9 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
 
   // one block for every array of the handle: the caller's workspace or ours
   const int n = h->n;
-  const Layout Ly = plan_layout(n, h->nnz, k, max_iter, h->async_mode, h->lane_max);
+  const bool bound_partials = cfg.workspace != nullptr;
+  const Layout Ly = plan_layout(n, h->nnz, k, max_iter, h->async_mode, h->lane_max,
+                                (cfg.flags & LPA_RESCAN) != 0, bound_partials);
   if (Ly.too_many_segs) return bail(set_err(h, LPA_ERR_UNSUPPORTED, "too many hub segments"));
   if (cfg.workspace) {
     if (cfg.workspace_bytes < Ly.total || ((uintptr_t)cfg.workspace & 255) != 0)
@@ -1398,6 +1407,16 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     hipLaunchKernelGGL(k_fill_seg_hub, dim3(grid_for(d.n_hubs)), dim3(kAuxBlock), 0, h->stream,
                        d.hub_pbase, d.n_hubs, (int32_t *)d.seg_hub);
     if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
+    if (!bound_partials && !streamed && nseg > 0) {  // partial sketches for exactly nseg
+      const size_t half = align_up((size_t)nseg * k * 4);
+      if (hipMalloc(&h->part_block, 2 * half) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(set_err(h, LPA_ERR_NOMEM, "hipMalloc failed (partial sketches)"));
+      }
+      h->core_bytes += 2 * half;
+      d.part_key = (int32_t *)h->part_block;
+      d.part_val = (float *)((char *)h->part_block + half);
+    }
   }
   d.hub_shared = (cfg.flags & LPA_HUB_SHARED) ? 1 : 0;
   d.items = h->async_mode ? ((d.hub_shared ? 0 : d.n_seg) + d.n_lane + kWave - 1) / kWave
