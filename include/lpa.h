@@ -137,7 +137,8 @@ typedef enum lpa_status {
  * to the unstreamed run; LPA_MODE_ASYNC runs the ranges in place like its
  * wavefronts.  Device memory: the library state, a second degree order (4 B
  * per vertex), the row offsets, each range's hub segments (async) and the
- * four buffers; not the graph.  lpa_run checks convergence after every
+ * four buffers; not the graph.  LPA_VALIDATE in lpa_init and lpa_modularity
+ * read the host arrays directly over the link (once per call).  lpa_run checks convergence after every
  * iteration; LPA_CAPTURE and lpa_batch_* do not apply (batches refuse such
  * handles with LPA_ERR_ARG). */
 #define LPA_STREAM_CSR 0x4000u
