@@ -171,10 +171,15 @@ constexpr int slots_of(int K) { return K == 0 ? 1 : K; }
 // slot % TW), stored at r * (TW + 1) + j.  The slots are taken kLoadBatch
 // at a time in three phases (column indices, weights, gathered labels), so
 // that each phase's loads are in flight together; a slot past its row's end
-// issues no load and is stored as padding (label -1, weight 0).
+// issues no load and is stored as padding (label -1, weight 0).  A step of
+// TW <= T / 2 leaves lab[] words 64 (TW + 1) onwards unused: with KEEP, slot
+// s's column index is kept at kept_col<TW>(s) there, for the marking pass.
 constexpr int kLoadBatch = 4;
 
-template <int TW, int T, class Pos>
+template <int TW>
+__device__ __forceinline__ int kept_col(int slot) { return kWave * (TW + 1) + slot; }
+
+template <int TW, bool KEEP, int T, class Pos>
 __device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T, Pos> &st, int lane, int t0) {
   constexpr int B = TW < kLoadBatch ? TW : kLoadBatch;
 #pragma unroll
@@ -203,6 +208,7 @@ __device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T, Pos> &st,
       const int r = slot / TW, j = slot % TW;
       st.lab[r * (TW + 1) + j] = lab[b];
       st.w[r * (TW + 1) + j] = c[b] == st.self[r] ? 0.0f : x[b];
+      if constexpr (KEEP && 2 * TW <= T) st.lab[kept_col<TW>(slot)] = c[b];
     }
   }
 }
@@ -212,10 +218,13 @@ __device__ __forceinline__ void stage_load(const MoveArgs &a, Stage<T, Pos> &st,
 // All lanes of the wavefront must call it together.  Each step takes 4, 8
 // or T entries per row, the narrowest that covers what the wavefront's
 // longest row has left: with short rows a wide step would leave most load
-// slots idle.
-template <int T, class Pos, class Feed>
-__device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
-                                            int len, int self, Feed &&feed) {
+// slots idle.  With KEEP, returns the step width when every row fit one
+// step of width 4 or 8 (the rows' column indices are then kept in the
+// stage); otherwise 0.  Keeping them costs registers: only kernels that
+// stay within their register budget with it pass KEEP.
+template <int T, bool KEEP = false, class Pos, class Feed>
+__device__ __forceinline__ int staged_rows(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
+                                           int len, int self, Feed &&feed) {
   st.beg[lane] = beg;
   st.len[lane] = len;
   st.self[lane] = self;
@@ -225,11 +234,11 @@ __device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T, Pos> &st
     const int rem = maxlen - t0;
     const int tw = rem <= 4 ? 4 : (rem <= 8 ? 8 : T);
     if (tw == 4)
-      stage_load<4>(a, st, lane, t0);
+      stage_load<4, KEEP>(a, st, lane, t0);
     else if (tw == 8)
-      stage_load<8>(a, st, lane, t0);
+      stage_load<8, KEEP>(a, st, lane, t0);
     else
-      stage_load<T>(a, st, lane, t0);
+      stage_load<T, KEEP>(a, st, lane, t0);
     wave_lds_sync();
     // this lane's row: its first tn staged entries (later columns of the
     // step are padding for every row: label -1, weight 0)
@@ -239,14 +248,15 @@ __device__ __forceinline__ void staged_rows(const MoveArgs &a, Stage<T, Pos> &st
     wave_lds_sync();
     t0 += tw;
   }
+  return KEEP && maxlen <= 8 && 16 <= T ? (maxlen <= 4 ? 4 : 8) : 0;
 }
 
 // Feed entries [beg, beg + len) of row `self` into S in CSR order (len = 0:
 // nothing).  All lanes of the wavefront must call it together.
-template <class SK, int T, class Pos>
-__device__ __forceinline__ void staged_scan(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
-                                            int len, int self, SK &S) {
-  staged_rows<T>(a, st, lane, beg, len, self, [&](int lab, float x) { S.add(lab, x); });
+template <class SK, int T, bool KEEP = false, class Pos>
+__device__ __forceinline__ int staged_scan(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
+                                           int len, int self, SK &S) {
+  return staged_rows<T, KEEP>(a, st, lane, beg, len, self, [&](int lab, float x) { S.add(lab, x); });
 }
 
 // Double scan (Section 4.4, Algorithm 4 rescan): the live slots of the
@@ -325,17 +335,42 @@ __device__ __forceinline__ void mark_row(const MoveArgs &a, Pos beg, Pos end, in
   }
 }
 
+// Mark from the column indices a single scan step of width TW kept in the
+// stage: each lane takes the slots it loaded (st.len already holds 0 for
+// rows that did not move).
+template <int TW, int T, class Pos>
+__device__ __forceinline__ void mark_kept(const MoveArgs &a, const Stage<T, Pos> &st, int lane) {
+#pragma unroll
+  for (int i = 0; i < TW; ++i) {
+    const int slot = i * kWave + lane;
+    const int r = slot / TW, j = slot % TW;
+    if (j < st.len[r]) mark(a, st.lab[kept_col<TW>(slot)]);
+  }
+}
+
 // Mark the neighbours of every lane whose `moved` is set (entries [beg, beg +
 // len) of its row), with row-contiguous column loads by the whole wavefront
-// and the same step widths as staged_rows.
+// and the same step widths as staged_rows.  kept = the width staged_rows
+// returned for these rows (the stage then still holds their column indices
+// and nothing is read from the CSR), or 0.
 template <int T, class Pos>
 __device__ __forceinline__ void staged_mark(const MoveArgs &a, Stage<T, Pos> &st, int lane, Pos beg,
-                                            int len, bool moved) {
+                                            int len, bool moved, int kept) {
   if (__ballot(moved) == 0ull) return;
   st.beg[lane] = beg;
   st.len[lane] = moved ? len : 0;
   const int maxlen = rfl(wave_max(moved ? len : 0));
   wave_lds_sync();
+  if (kept == 4) {
+    mark_kept<4>(a, st, lane);
+    wave_lds_sync();
+    return;
+  }
+  if (kept == 8) {
+    mark_kept<8>(a, st, lane);
+    wave_lds_sync();
+    return;
+  }
   for (int t0 = 0; t0 < maxlen;) {
     const int rem = maxlen - t0;
     if (rem <= 4) {
@@ -642,7 +677,7 @@ __device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &
 // hub h = seg_hub[u] (async only); otherwise whole vertex order[n_hubs + u -
 // n_seg].
 // ---------------------------------------------------------------------------
-template <int K, bool ASYNC, bool RS, class Pos>
+template <int K, bool ASYNC, bool RS, class Pos, bool KEEP>
 __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos> &st, int u,
                                            unsigned long long &scanned,
                                            unsigned long long &changed) {
@@ -673,7 +708,7 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
   if (!active) len = 0;
   typename SketchOf<K>::type S;
   S.clear();
-  staged_scan<typename SketchOf<K>::type, kStageT>(a, st, lane, beg, len, v, S);
+  const int kept = staged_scan<typename SketchOf<K>::type, kStageT, KEEP>(a, st, lane, beg, len, v, S);
   scanned += (unsigned long long)len;
   int c = cv;
   if constexpr (RS) {
@@ -707,7 +742,7 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
   }
   // every lane reaches here: the marking pass is wavefront-cooperative
   changed += (unsigned long long)__popcll(__ballot(moved));
-  staged_mark<kStageT>(a, st, lane, beg, len, moved);
+  staged_mark<kStageT>(a, st, lane, beg, len, moved, kept);
 }
 
 // ---------------------------------------------------------------------------
@@ -767,6 +802,13 @@ __device__ __forceinline__ void flush_counts(unsigned long long *dN, unsigned lo
   scanned_lane = scanned_w = changed_w = 0;
 }
 
+// Lane units keep narrow rows' column indices in the stage for marking
+// (staged_rows) only in the kernels that still fit 128 registers with it:
+// single scan, sketch votes, 32-bit positions, k <= 8.  Elsewhere the extra
+// registers would cost a wavefront per SIMD, which the gathers need more.
+template <int K, bool RS, class Pos, bool SV>
+constexpr bool kKeepCols = !RS && !SV && sizeof(Pos) == 4 && K <= 8;
+
 template <int K, bool ASYNC, bool RS, class Pos, bool SV = false>
 __device__ __forceinline__ void move_body(const Launch &L) {
   __shared__ Stage<kStageT, Pos> stage[kBlock / kWave];
@@ -799,8 +841,8 @@ __device__ __forceinline__ void move_body(const Launch &L) {
       else
         hub_vertex_det<K, RS, Pos>(a, a.order[local], scanned_w, changed_w);
     } else
-      lane_units<K, ASYNC, RS, Pos>(a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane,
-                               changed_w);
+      lane_units<K, ASYNC, RS, Pos, kKeepCols<K, RS, Pos, SV>>(
+          a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane, changed_w);
   }
   flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
 }
