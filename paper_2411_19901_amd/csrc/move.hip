@@ -902,10 +902,21 @@ __device__ __forceinline__ void record_moved_hub(const MoveArgs &a, int h, bool 
   if (h < a.n_hubs) a.hub_act[h] = moved ? 1 : 0;
 }
 
+// Hub taken by lane group `grp` of merge item `it` of a graph with `ni`
+// merge items: hubs are dealt out across the items (group j of item i takes
+// hub j * ni + i).  The largest hubs sit next to each other in the degree
+// order; dealt out, each lands in a wavefront of its own instead of one
+// wavefront merging them one after another.
+__device__ __forceinline__ int merge_hub(int it, int grp, int ni) { return grp * ni + it; }
+
+__device__ __forceinline__ int merge_items(const Launch &L, int g) {
+  return L.prefix_merge[g + 1] - L.prefix_merge[g];
+}
+
 // Merge the partial sketches of every active hub (Section 4.3).  A wavefront
-// takes kMergeHubs hubs of one graph, kHubLanes lanes each.  For a hub with
-// at most 64 partials the partials are fed one by one, in segment order,
-// into a single sketch, which every lane of the group computes alike: lane
+// takes kMergeHubs hubs of one graph (merge_hub), kHubLanes lanes each.  For
+// a hub with at most 64 partials the partials are fed one by one, in segment
+// order, into a single sketch, which every lane of the group computes alike: lane
 // t of the group loads partials t, t + kHubLanes, ... (the next one's loads
 // in flight) and hands each over by a lane exchange.  Feeding every partial
 // into one sketch follows the paper's merge into the first group's sketch;
@@ -937,7 +948,8 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
       cdN = gd.dN + iter;
     }
     const MoveArgs a = make_args(gd, iter);
-    const int h = (item - L.prefix_merge[g]) * kMergeHubs + lane / kHubLanes;
+    const int it = item - L.prefix_merge[g], ni = rfl(merge_items(L, g));
+    const int h = merge_hub(it, lane / kHubLanes, ni);
     int v = -1, p0 = 0, np = 0, cv = 0;
     bool active = false;
     if (h < a.n_hubs) {
@@ -1035,7 +1047,7 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
         B.merge_from(pk, pv);
       }
       if constexpr (RS) {
-        const int bh = (item - L.prefix_merge[g]) * kMergeHubs + src / kHubLanes;
+        const int bh = merge_hub(it, src / kHubLanes, ni);
         if (lane == 0) {
 #pragma unroll
           for (int s = 0; s < P; ++s)
@@ -1126,7 +1138,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
 
 // Double scan, hub decision: add up the segments' candidate weights, take
 // the heaviest candidate (ties to the lowest label), update the label and
-// flag the neighbours.  Same hub-to-lane layout as k_hub_merge.
+// flag the neighbours.  Same hub-to-lane layout as k_hub_merge (merge_hub).
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -1147,7 +1159,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
       cdN = gd.dN + iter;
     }
     const MoveArgs a = make_args(gd, iter);
-    const int h = (item - L.prefix_merge[g]) * kMergeHubs + lane / kHubLanes;
+    const int it = item - L.prefix_merge[g], ni = rfl(merge_items(L, g));
+    const int h = merge_hub(it, lane / kHubLanes, ni);
     int v = -1, p0 = 0, np = 0, cv = 0;
     bool active = false;
     if (h < a.n_hubs) {
