@@ -803,11 +803,13 @@ __device__ __forceinline__ void flush_counts(unsigned long long *dN, unsigned lo
 }
 
 // Lane units keep narrow rows' column indices in the stage for marking
-// (staged_rows) only in the kernels that still fit 128 registers with it:
-// single scan, sketch votes, 32-bit positions, k <= 8.  Elsewhere the extra
-// registers would cost a wavefront per SIMD, which the gathers need more.
+// (staged_rows) only in the kernels whose wavefronts per SIMD it leaves
+// unchanged: single scan, sketch votes, 32-bit positions (k <= 8 stays
+// within 128 registers, k = 16 within 168, k = 32 within 256).  In the
+// 64-bit, double-scan and shared-variable kernels the extra registers would
+// cost a wavefront per SIMD, which the gathers need more.
 template <int K, bool RS, class Pos, bool SV>
-constexpr bool kKeepCols = !RS && !SV && sizeof(Pos) == 4 && K <= 8;
+constexpr bool kKeepCols = !RS && !SV && sizeof(Pos) == 4;
 
 template <int K, bool ASYNC, bool RS, class Pos, bool SV = false>
 __device__ __forceinline__ void move_body(const Launch &L) {
