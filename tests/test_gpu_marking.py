@@ -68,7 +68,7 @@ def test_graphs_sit_on_the_widths(cap):
 
 
 @pytest.mark.parametrize("cap", CAPS)
-@pytest.mark.parametrize("k", [1, 4, 8, 16])
+@pytest.mark.parametrize("k", [1, 4, 8, 16, 32])
 def test_det_parity_short_rows(cap, k):
     check_det(graph(cap), k)
 
@@ -91,10 +91,11 @@ def test_det_parity_short_rows_no_pickless(cap):
 
 
 @pytest.mark.parametrize("cap", CAPS)
-def test_async_short_rows(cap):
+@pytest.mark.parametrize("k", [8, 32])
+def test_async_short_rows(cap, k):
     g = graph(cap)
     rp, col, w = to_dev(g)
-    s = lpa.LPA(rp, col, w, k=8, mode="async")
+    s = lpa.LPA(rp, col, w, k=k, mode="async")
     it = s.run()
     lab = s.labels(device=False)
     dn, sc = s.trace()
