@@ -317,20 +317,22 @@ __device__ __forceinline__ void mark_step(const MoveArgs &a, const Stage<T, Pos>
 }
 
 // Mark the neighbours of entries [beg, end) of one row, the whole wavefront
-// taking 64 x kMarkUnroll entries at a time (loads first, then stores).
+// taking 64 x U entries at a time (loads first, then stores).  The move
+// kernels use kMarkUnroll; k_hub_mark, which only marks, takes a whole hub
+// segment per step so that one load latency is waited for per segment.
 constexpr int kMarkUnroll = 4;
 
-template <class Pos>
+template <int U = kMarkUnroll, class Pos>
 __device__ __forceinline__ void mark_row(const MoveArgs &a, Pos beg, Pos end, int lane) {
-  for (Pos q0 = beg; q0 < end; q0 += kMarkUnroll * kWave) {
-    int c[kMarkUnroll];
+  for (Pos q0 = beg; q0 < end; q0 += U * kWave) {
+    int c[U];
 #pragma unroll
-    for (int u = 0; u < kMarkUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const Pos q = q0 + u * kWave + lane;
       c[u] = q < end ? __builtin_nontemporal_load(a.col + q) : -1;
     }
 #pragma unroll
-    for (int u = 0; u < kMarkUnroll; ++u)
+    for (int u = 0; u < U; ++u)
       if (c[u] >= 0) mark(a, c[u]);
   }
 }
@@ -1239,7 +1241,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_mark(Launch L) {
     const int q = u - a.hub_pbase[h];
     const long long rb = a.row_ptr[v], re = a.row_ptr[v + 1];
     const long long beg = rb + (long long)q * a.seg_len, end = min(beg + a.seg_len, re);
-    mark_row(a, beg, end, lane);
+    mark_row<16>(a, beg, end, lane);
   }
 }
 
