@@ -179,3 +179,32 @@ def modularity(row_ptr, col, w, labels) -> float:
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def hub_segment_choice(row_ptr, col, w, k: int, seg_len: int, C, v: int) -> int:
+    """Label vertex ``v`` picks from partial sketches (Section 4.3, merging
+    the per-group sketches of a high-degree vertex): its row is cut into
+    consecutive segments of ``seg_len`` entries; each segment's neighbours
+    (the vertex itself skipped) are fed in CSR order into a k-slot sketch of
+    their own; then the live slots of those partial sketches, segment by
+    segment and slot by slot, are fed into one fresh sketch, and its
+    heaviest label wins (ties to the lowest label; an empty sketch keeps
+    ``C[v]``).  Whether the vertex adopts it (pick-less rule) is the
+    caller's."""
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    b, e = int(row_ptr[v]), int(row_ptr[v + 1])
+    keys, vals = [], []
+    for s0 in range(b, e, seg_len):
+        s1 = min(e, s0 + seg_len)
+        nb = col[s0:s1]
+        keep = nb != v
+        lab = np.asarray(C, dtype=np.int32)[nb[keep]]
+        wt = None if w is None else w[s0:s1][keep]
+        pk, pv = sketch_feed(k, lab, wt)
+        live = pv > 0.0
+        keys.append(pk[live])
+        vals.append(pv[live])
+    if not keys:
+        return int(C[v])
+    mk, mv = sketch_feed(k, np.concatenate(keys), np.concatenate(vals))
+    return sketch_max_key(mk, mv, int(C[v]))
