@@ -181,30 +181,55 @@ def max_threads() -> int:
     return int(lib().orc_max_threads())
 
 
-def hub_segment_choice(row_ptr, col, w, k: int, seg_len: int, C, v: int) -> int:
-    """Label vertex ``v`` picks from partial sketches (Section 4.3, merging
-    the per-group sketches of a high-degree vertex): its row is cut into
-    consecutive segments of ``seg_len`` entries; each segment's neighbours
-    (the vertex itself skipped) are fed in CSR order into a k-slot sketch of
-    their own; then the live slots of those partial sketches, segment by
-    segment and slot by slot, are fed into one fresh sketch, and its
-    heaviest label wins (ties to the lowest label; an empty sketch keeps
-    ``C[v]``).  Whether the vertex adopts it (pick-less rule) is the
-    caller's."""
+def hub_merged_sketch(row_ptr, col, w, k: int, seg_len: int, C, v: int):
+    """Merged partial sketch of vertex ``v`` (Section 4.3): its row cut into
+    segments of ``seg_len`` entries, each summarised by a k-slot sketch in
+    CSR order (``v`` itself skipped); up to 64 partials are fed, segment by
+    segment and live slot by live slot, into one sketch; above 64, partial q
+    goes to chain q mod 64 and the 64 chains are combined pairwise in rounds
+    at distances 32, 16, ..., 1 (chain t absorbs what chain t ^ distance held
+    at the start of the round), the result being chain 0.  Returns (keys,
+    vals, segments)."""
     row_ptr, col, w = _csr(row_ptr, col, w)
-    b, e = int(row_ptr[v]), int(row_ptr[v + 1])
-    keys, vals = [], []
-    for s0 in range(b, e, seg_len):
-        s1 = min(e, s0 + seg_len)
-        nb = col[s0:s1]
-        keep = nb != v
-        lab = np.asarray(C, dtype=np.int32)[nb[keep]]
-        wt = None if w is None else w[s0:s1][keep]
-        pk, pv = sketch_feed(k, lab, wt)
-        live = pv > 0.0
-        keys.append(pk[live])
-        vals.append(pv[live])
-    if not keys:
-        return int(C[v])
-    mk, mv = sketch_feed(k, np.concatenate(keys), np.concatenate(vals))
-    return sketch_max_key(mk, mv, int(C[v]))
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    f = lib().orc_hub_merged_sketch
+    f.argtypes = [_i32p, _i32p, _f32p, ctypes.c_int, ctypes.c_int32, _i32p, ctypes.c_int32,
+                  _i32p, _f32p]
+    f.restype = ctypes.c_int64
+    key = np.empty(k, np.int32)
+    val = np.empty(k, np.float32)
+    np_ = f(_p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, seg_len, _p(C, _i32p), v,
+            _p(key, _i32p), _p(val, _f32p))
+    if np_ < 0:
+        raise ValueError("oracle rejected its arguments")
+    return key, val, int(np_)
+
+
+def hub_segment_choice(row_ptr, col, w, k: int, seg_len: int, C, v: int) -> int:
+    """Label vertex ``v`` picks from its merged partial sketch
+    (``hub_merged_sketch``): the heaviest label, ties to the lowest, an empty
+    sketch keeps ``C[v]``.  Whether the vertex adopts it (pick-less rule) is
+    the caller's."""
+    key, val, _ = hub_merged_sketch(row_ptr, col, w, k, seg_len, C, v)
+    return sketch_max_key(key, val, int(C[v]))
+
+
+def hub_choose(row_ptr, col, w, k: int, seg_len: int, pickless: bool, C, verts,
+               rescan: bool = False, nthreads: int = 0):
+    """Label each vertex in ``verts`` holds after one iteration in which it is
+    processed through its partial sketches (``hub_merged_sketch``): the
+    merged sketch's heaviest label, or with ``rescan`` its live labels
+    re-weighted exactly over the whole row (Section 4.4), adopted under the
+    pick-less rule."""
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    n = len(row_ptr) - 1
+    C = np.ascontiguousarray(C, dtype=np.int32)
+    verts = np.ascontiguousarray(verts, dtype=np.int32)
+    out = np.empty(len(verts), np.int32)
+    f = lib().orc_hub_choose
+    f.argtypes = [ctypes.c_int32, _i32p, _i32p, _f32p, ctypes.c_int, ctypes.c_int, ctypes.c_int32,
+                  ctypes.c_int, _i32p, ctypes.c_int64, _i32p, _i32p, ctypes.c_int]
+    f.restype = None
+    f(n, _p(row_ptr, _i32p), _p(col, _i32p), _p(w, _f32p), k, int(rescan), seg_len,
+      int(pickless), _p(C, _i32p), len(verts), _p(verts, _i32p), _p(out, _i32p), nthreads)
+    return out

@@ -30,6 +30,11 @@
  *      by pick-less is still processed.
  *   R5 N in dN/N is |V| (isolated vertices included); the comparison is
  *      strict and evaluated in double.
+ *   R7 a pair goes to the slot whose label it carries even when a decrement
+ *      has emptied that slot (Algorithm 2 compares labels only); a new label
+ *      takes the lowest free slot; a pair of weight 0 changes nothing.
+ *   R9 the merge order of a high-degree vertex's partial sketches (Section
+ *      4.3 leaves it open): see orc_hub_merged_sketch.
  *   The paper's own Boyer-Moore rule (Algorithm 3) is available as a second
  *   per-vertex rule (k == ORC_BM_PAPER), run by the same Jacobi driver.
  *   R14 double scan (Section 4.4; Algorithm 4 rescan): the candidates are the
@@ -63,14 +68,19 @@ void orc_sketch_clear(int k, int32_t *key, float *val) {
 
 void orc_sketch_accumulate(int k, int32_t *key, float *val, int32_t c,
                            float w) {
-  /* label already a live candidate: add the weight to its slot */
+  /* a pair of weight zero changes nothing (reading R11) */
+  if (w == 0.0f) return;
+  /* the slot whose label is c takes the weight, whatever its value: the
+   * first test of Algorithm 2 looks at the slot's label only, so a label
+   * whose slot was emptied by a decrement returns to that same slot */
   for (int s = 0; s < k; ++s) {
-    if (val[s] > 0.0f && key[s] == c) {
+    if (key[s] == c) {
       val[s] = val[s] + w;
       return;
     }
   }
-  /* a free slot (value zero) takes the pair */
+  /* otherwise the lowest free slot (value zero) takes the pair: the first
+   * set bit of Algorithm 2's free-slot ballot */
   for (int s = 0; s < k; ++s) {
     if (val[s] == 0.0f) {
       key[s] = c;
@@ -83,7 +93,8 @@ void orc_sketch_accumulate(int k, int32_t *key, float *val, int32_t c,
   for (int s = 0; s < k; ++s)
     if (val[s] < d) d = val[s];
   for (int s = 0; s < k; ++s) val[s] = val[s] - d;
-  /* what is left of w (if anything) goes into a slot that just emptied */
+  /* what is left of w (if anything) goes into the lowest slot that just
+   * emptied */
   float r = w - d;
   if (r > 0.0f) {
     for (int s = 0; s < k; ++s) {
@@ -383,6 +394,133 @@ void orc_lpa_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
     }
     free(acc);
     free(touched);
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Partial sketches of a high-degree vertex (Section 4.3; reading R9).     */
+/* ---------------------------------------------------------------------- */
+
+/* Feed the live slots of sketch (pk, pv) into (key, val), slot by slot. */
+static void feed_live(int k, int32_t *key, float *val, const int32_t *pk,
+                      const float *pv) {
+  for (int s = 0; s < k; ++s)
+    if (pv[s] > 0.0f) orc_sketch_accumulate(k, key, val, pk[s], pv[s]);
+}
+
+/* Sketch of segment q of vertex v's row: entries [b + q S, b + (q+1) S)
+ * in CSR order, the vertex itself skipped. */
+static void segment_sketch(const int32_t *row_ptr, const int32_t *col,
+                           const float *w, int k, int32_t seg_len,
+                           const int32_t *C, int32_t v, int64_t q,
+                           int32_t *key, float *val) {
+  int64_t b = (int64_t)row_ptr[v] + q * seg_len;
+  int64_t e = b + seg_len;
+  if (e > row_ptr[v + 1]) e = row_ptr[v + 1];
+  orc_sketch_clear(k, key, val);
+  for (int64_t t = b; t < e; ++t) {
+    if (col[t] == v) continue;
+    orc_sketch_accumulate(k, key, val, C[col[t]], w ? w[t] : 1.0f);
+  }
+}
+
+int64_t orc_hub_merged_sketch(const int32_t *row_ptr, const int32_t *col,
+                              const float *w, int k, int32_t seg_len,
+                              const int32_t *C, int32_t v, int32_t *key,
+                              float *val) {
+  if (k < 1 || k > 64 || seg_len < 1) return -1;
+  const int64_t deg = (int64_t)row_ptr[v + 1] - row_ptr[v];
+  const int64_t np = (deg + seg_len - 1) / seg_len;
+  int32_t pk[64];
+  float pv[64];
+  orc_sketch_clear(k, key, val);
+  if (np <= ORC_MERGE_CHAINS) {
+    /* every partial, in segment order, into one sketch */
+    for (int64_t q = 0; q < np; ++q) {
+      segment_sketch(row_ptr, col, w, k, seg_len, C, v, q, pk, pv);
+      feed_live(k, key, val, pk, pv);
+    }
+    return np;
+  }
+  /* ORC_MERGE_CHAINS chains: chain t takes partials t, t + 64, t + 128, ...
+   * in that order; then rounds at distance 32, 16, 8, 4, 2, 1, in each of
+   * which every chain t absorbs what chain t ^ distance held at the start
+   * of the round; the result is chain 0 */
+  const int nc = ORC_MERGE_CHAINS;
+  int32_t *ck = (int32_t *)malloc((size_t)nc * k * sizeof(int32_t));
+  float *cw = (float *)malloc((size_t)nc * k * sizeof(float));
+  int32_t *sk = (int32_t *)malloc((size_t)nc * k * sizeof(int32_t));
+  float *sw = (float *)malloc((size_t)nc * k * sizeof(float));
+  if (!ck || !cw || !sk || !sw) {
+    free(ck);
+    free(cw);
+    free(sk);
+    free(sw);
+    return -1;
+  }
+  for (int t = 0; t < nc; ++t) orc_sketch_clear(k, ck + t * k, cw + t * k);
+  for (int64_t q = 0; q < np; ++q) {
+    const int t = (int)(q % nc);
+    segment_sketch(row_ptr, col, w, k, seg_len, C, v, q, pk, pv);
+    feed_live(k, ck + t * k, cw + t * k, pk, pv);
+  }
+  for (int dist = nc / 2; dist >= 1; dist /= 2) {
+    memcpy(sk, ck, (size_t)nc * k * sizeof(int32_t));
+    memcpy(sw, cw, (size_t)nc * k * sizeof(float));
+    for (int t = 0; t < nc; ++t)
+      feed_live(k, ck + t * k, cw + t * k, sk + (t ^ dist) * k, sw + (t ^ dist) * k);
+  }
+  memcpy(key, ck, (size_t)k * sizeof(int32_t));
+  memcpy(val, cw, (size_t)k * sizeof(float));
+  free(ck);
+  free(cw);
+  free(sk);
+  free(sw);
+  return np;
+}
+
+/* Choice of a high-degree vertex from its merged partial sketch: the
+ * heaviest slot; with rescan, the merged sketch's live labels re-weighted
+ * exactly over the whole row (fp32 sums in CSR order). */
+static int32_t choose_hub(const int32_t *row_ptr, const int32_t *col,
+                          const float *w, int k, int rescan, int32_t seg_len,
+                          const int32_t *C, int32_t v) {
+  int32_t key[64];
+  float val[64];
+  if (orc_hub_merged_sketch(row_ptr, col, w, k, seg_len, C, v, key, val) < 0)
+    return C[v];
+  if (!rescan) return orc_sketch_max_key(k, key, val, C[v]);
+  float sum[64];
+  for (int s = 0; s < k; ++s) sum[s] = 0.0f;
+  for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+    if (col[e] == v) continue;
+    for (int s = 0; s < k; ++s)
+      if (val[s] > 0.0f && key[s] == C[col[e]]) sum[s] = sum[s] + (w ? w[e] : 1.0f);
+  }
+  int32_t best = C[v];
+  float bv = 0.0f;
+  int found = 0;
+  for (int s = 0; s < k; ++s) {
+    if (sum[s] > 0.0f && (!found || sum[s] > bv || (sum[s] == bv && key[s] < best))) {
+      best = key[s];
+      bv = sum[s];
+      found = 1;
+    }
+  }
+  return best;
+}
+
+void orc_hub_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                    const float *w, int k, int rescan, int32_t seg_len,
+                    int pickless, const int32_t *C, int64_t nv,
+                    const int32_t *verts, int32_t *out, int nthreads) {
+  (void)n;
+  int nt = resolve_threads(nthreads);
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 4)
+  for (int64_t q = 0; q < nv; ++q) {
+    int32_t i = verts[q];
+    int32_t c = choose_hub(row_ptr, col, w, k, rescan, seg_len, C, i);
+    out[q] = (c != C[i] && (!pickless || c < C[i])) ? c : C[i];
   }
 }
 

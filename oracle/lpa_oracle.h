@@ -72,6 +72,31 @@ void orc_lpa_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
                     int64_t nv, const int32_t *verts, int32_t *out,
                     int nthreads);
 
+/* Partial sketches of a high-degree vertex v (Section 4.3; reading R9): its
+ * row is cut into segments of seg_len entries, each fed in CSR order (v
+ * itself skipped) into a k-slot sketch of its own.  Up to
+ * ORC_MERGE_CHAINS segments, the partials' live slots are fed, segment by
+ * segment and slot by slot, into one sketch.  Above that, partial q goes to
+ * chain q mod ORC_MERGE_CHAINS (each chain fed in segment order), and the
+ * chains are then combined in rounds at distances 32, 16, ..., 1: in each
+ * round chain t is fed the live slots chain t ^ distance held at the start
+ * of the round; the merged sketch is chain 0.  Writes it to key/val (k
+ * entries) and returns the number of segments (-1: bad arguments). */
+#define ORC_MERGE_CHAINS 64
+int64_t orc_hub_merged_sketch(const int32_t *row_ptr, const int32_t *col,
+                              const float *w, int k, int32_t seg_len,
+                              const int32_t *C, int32_t v, int32_t *key,
+                              float *val);
+
+/* For each listed vertex, the label it holds after one iteration when it is
+ * processed through its partial sketches: the merged sketch's heaviest
+ * label (rescan: its live labels re-weighted exactly over the whole row),
+ * adopted under the pick-less rule. */
+void orc_hub_choose(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                    const float *w, int k, int rescan, int32_t seg_len,
+                    int pickless, const int32_t *C, int64_t nv,
+                    const int32_t *verts, int32_t *out, int nthreads);
+
 /* Modularity Q of Eq. 1 (community-sum form) in fp64. */
 double orc_modularity(int32_t n, const int32_t *row_ptr, const int32_t *col,
                       const float *w, const int32_t *C);

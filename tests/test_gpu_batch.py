@@ -155,3 +155,39 @@ def test_batch_reset_equals_reset():
     batch.close()
     for s in solvers:
         s.close()
+
+
+_big = {}
+
+
+def batch512():
+    """The many-graph workload at full size: 512 planted-partition graphs
+    (seed 512, n log-uniform in [1e3, 2e5]; 21.7M vertices, 304M entries),
+    with the oracle's whole run of each."""
+    if not _big:
+        specs = inputs.batch_specs(512, 512)
+        gs = [inputs.batch_graph(s, 512, i) for i, s in enumerate(specs)]
+        _big["gs"] = gs
+        _big["refs"] = [oracle.lpa_run(g.row_ptr, g.col, None, k=8) for g in gs]
+    return _big["gs"], _big["refs"]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("capture", [False, True])
+def test_batch512_every_graph_matches_oracle(capture):
+    gs, refs = batch512()
+    d = dev()
+    stream = torch.cuda.current_stream(d)
+    solvers = [make_solver(g, stream=stream) for g in gs]
+    batch = lpa.Batch(len(solvers), k=8, mode="det", stream=stream, capture=capture)
+    for rep in range(2):  # a second batched solve from a one-launch reset
+        batch.reset(solvers)
+        batch.run(solvers)
+        for g, s, (ref, rit, rdn, rsc) in zip(gs, solvers, refs):
+            assert s.iterations() == rit, (g.name, rep)
+            dn, sc = s.trace()
+            assert np.array_equal(dn, rdn) and np.array_equal(sc, rsc), (g.name, rep)
+            assert np.array_equal(s.labels(device=False), ref), (g.name, rep)
+    batch.close()
+    for s in solvers:
+        s.close()

@@ -2,12 +2,15 @@
 
 * R-MAT scale 22 (128M CSR entries), det mode: every iteration is checked in
   full against the oracle's one-iteration function from the same state —
-  labels, next flags and changed count, bit for bit.
-* R-MAT scale 24 (0.52B entries, weights uniform in (0, 1]), det mode: two
-  iterations, checked on 200,000 sampled vertices plus every vertex of
-  degree above 4096 (the oracle chooses their labels one by one).
+  labels, next flags and changed count, bit for bit (k = 8); whole runs
+  against the oracle's whole run for the other sketch sizes of the k sweep
+  (k = 1, 4, 16), the vote of Algorithm 3 and the double scan.
+* R-MAT scale 24 (0.52B entries, weights uniform in (0, 1]), det mode: the
+  whole run against the oracle's whole run (labels, iterations, changed and
+  scanned counts of every iteration).
 * Modularity of the asynchronous run on R-MAT scale 24 (the benchmark
   configuration) against the oracle's fp64 modularity of the same labels.
+* The 4096 x 4096 rewired grid, det mode, whole run.
 """
 import numpy as np
 import pytest
@@ -62,25 +65,33 @@ def test_rmat22_det_every_iteration_exact():
     s.close()
 
 
-@pytest.mark.timeout(600)
-def test_rmat24_det_sampled():
-    g = graph(24, True)
-    s = solver(g, k=8, mode="det")
-    deg = g.degrees()
-    rng = np.random.default_rng(24)
-    nz = np.nonzero(deg > 0)[0]
-    sample = np.unique(np.concatenate([rng.choice(nz, 200_000, replace=False),
-                                       np.nonzero(deg > 4096)[0]])).astype(np.int32)
-    for _ in range(2):
-        C, act, l = s.get_state()
-        s.step()
-        C2, _, _ = s.get_state()
-        pl = l % 8 == 0
-        chosen = oracle.lpa_choose(g.row_ptr, g.col, g.w, 8, pl, C, sample)
-        expect = np.where(act[sample] != 0, chosen, C[sample])
-        bad = np.nonzero(C2[sample] != expect)[0]
-        assert bad.size == 0, (l, sample[bad[:5]], C2[sample[bad[:5]]], expect[bad[:5]])
+def whole_run_exact(g, k, **kw):
+    s = solver(g, k=k, mode="det", **kw)
+    it = s.run()
+    ref, rit, rdn, rsc = oracle.lpa_run(g.row_ptr, g.col, g.w, k=k, rescan=kw.get("rescan", False))
+    assert it == rit, (it, rit)
+    dn, sc = s.trace()
+    assert np.array_equal(dn, rdn) and np.array_equal(sc, rsc), (dn, rdn, sc, rsc)
+    lab = s.labels(device=False)
+    bad = np.nonzero(lab != ref)[0]
+    assert bad.size == 0, (bad.size, bad[:5], lab[bad[:5]], ref[bad[:5]])
+    q = s.modularity()
+    assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, ref)) <= 1e-9
     s.close()
+    return it
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_rmat22_det_whole_run_k_sweep(k):
+    it = whole_run_exact(graph(22, False), k)
+    print(f"rmat22 det k={k}: {it} iterations equal to the oracle")
+
+
+@pytest.mark.timeout(900)
+def test_rmat24_det_whole_run():
+    it = whole_run_exact(graph(24, True), 8)
+    print(f"rmat24 det k=8: {it} iterations equal to the oracle")
 
 
 @pytest.mark.timeout(600)

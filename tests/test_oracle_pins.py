@@ -71,8 +71,10 @@ def test_p1_counterexample_literal_rule_breaks_guarantee(orc):
 
 # ---------------------------------------------------------------- P2
 def paper_alg2_unit(k, stream):
-    """Algorithm 2, non-shared, unit weights, as printed (decrement every
-    slot by w when the label is absent and no slot is free)."""
+    """Algorithm 2, non-shared, unit weights, as printed: a slot whose label
+    is c takes the weight (its value is not looked at); otherwise the first
+    free slot (value 0) takes (c, 1); otherwise every slot loses 1.
+    Returns the slots (label, value) in slot order."""
     key = [-1] * k
     val = [0] * k
     for c in stream:
@@ -90,15 +92,30 @@ def paper_alg2_unit(k, stream):
         else:
             for s in range(k):
                 val[s] -= 1
-    return {key[s]: float(val[s]) for s in range(k) if val[s] != 0}
+    return key, val
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_p2_unit_weights_equal_paper_algorithm2(orc, k):
+    # slot for slot, emptied slots' labels included: the order of the slots
+    # is what a merge of partial sketches feeds on (Section 4.3)
     for L in range(0, 8):
         for stream in itertools.product(range(4), repeat=L):
             keys, vals = orc.sketch_feed(k, list(stream))
-            assert live(keys, vals) == paper_alg2_unit(k, stream), stream
+            pk, pv = paper_alg2_unit(k, stream)
+            assert keys.tolist() == pk, stream
+            assert vals.tolist() == [float(x) for x in pv], stream
+
+
+def test_p2_emptied_slot_keeps_its_label(orc):
+    # k = 2, unit weights: a, b fill both slots, c empties both (a and b
+    # keep their labels at value 0), then b returns to slot 1 -- not to the
+    # lowest free slot 0 -- and d takes slot 0 (Algorithm 2)
+    keys, vals = orc.sketch_feed(2, [7, 8, 9, 8, 5])
+    assert keys.tolist() == [5, 8] and vals.tolist() == [1.0, 1.0]
+    # weight 0 changes nothing, not even an empty slot's label
+    keys, vals = orc.sketch_feed(2, [7, 3], [0.0, 1.0])
+    assert keys.tolist() == [3, -1] and vals.tolist() == [1.0, 0.0]
 
 
 # ---------------------------------------------------------------- P3
