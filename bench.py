@@ -68,11 +68,13 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(g, k, seconds, rng_seed=0):
+def cpu_baseline(g, k, seconds, rng_seed=0, exact_run=False):
     """Oracle label choice (iteration 0, CSR order; k slots, or k=-1 for the
     vote of Algorithm 3) on a random vertex sample sized for about `seconds`
     of work on all host threads, plus the same on one thread for a sample a
-    quarter as long."""
+    quarter as long.  exact_run: also the oracle's whole Jacobi run with the
+    exact rule of Eq. 3 on the full graph (all host threads), with the
+    modularity of its labels: the quality reference of the async mode."""
     import numpy as np
     import oracle
 
@@ -109,7 +111,18 @@ def cpu_baseline(g, k, seconds, rng_seed=0):
     tx = time.perf_counter()
     oracle.lpa_choose(g.row_ptr, g.col, g.w, 0, True, C, ex)
     dtx = max(time.perf_counter() - tx, 1e-6)
-    return {"value": round(edges / dt / 1e9, 4), "unit": "GTEPS", "cores": int(nt),
+    res_exact = None
+    if exact_run:
+        tx = time.perf_counter()
+        lab, it, _, sc = oracle.lpa_run(g.row_ptr, g.col, g.w, k=0)
+        dt_run = max(time.perf_counter() - tx, 1e-6)
+        res_exact = {"q": round(oracle.modularity(g.row_ptr, g.col, g.w, lab), 6),
+                     "iterations": int(it), "seconds": round(dt_run, 2),
+                     "GTEPS": round(int(sc.sum()) / dt_run / 1e9, 4),
+                     "communities": int(len(np.unique(lab))),
+                     "what": "whole Jacobi run with the exact argmax of Eq. 3 (tol 0.05, "
+                             "max 20 iterations, pick-less every 8), full graph"}
+    out = {"value": round(edges / dt / 1e9, 4), "unit": "GTEPS", "cores": int(nt),
             "kind": "oracle",
             "sample": f"{len(sample)} uniformly sampled non-isolated vertices ({edges} CSR entries, "
                       f"{100.0 * edges / g.nnz:.1f}% of the graph), one iteration-0 label choice each, "
@@ -119,6 +132,38 @@ def cpu_baseline(g, k, seconds, rng_seed=0):
             "exact_rule": {"value": round(edges_x / dtx / 1e9, 4), "unit": "GTEPS", "cores": int(nt),
                            "sample": f"{len(ex)} vertices ({edges_x} CSR entries), exact argmax "
                                      f"of Eq. 3, {dtx:.1f} s"}}
+    if res_exact is not None:
+        out["exact_rule_run"] = res_exact
+    return out
+
+
+def timed_solves(solver, steps, warmup, tag=""):
+    """Warm-up solves, then `steps` timed solves (lpa_reset + lpa_run each)
+    with the move kernel's HIP events on; returns the whole-job and kernel
+    figures of the timed region."""
+    import torch
+
+    for i in range(warmup):
+        solver.reset()
+        it = solver.run()
+        log(f"[bench]{tag} warmup {i}: {it} iterations")
+    edges_total, kernel_ms, launches, iters = 0, 0.0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.reset()
+        it = solver.run()
+        _, sc = solver.trace()
+        ms = solver.move_ms()
+        iters.append(it)
+        edges_total += int(sc.sum())
+        kernel_ms += float(ms.sum())
+        launches += len(ms)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench]{tag} timed {steps} steps in {elapsed:.3f}s; iterations {iters}")
+    return {"edges": edges_total, "elapsed": elapsed, "kernel_ms": kernel_ms,
+            "launches": launches, "iters": iters}
 
 
 def build_graph(args):
@@ -147,10 +192,11 @@ def build_graph(args):
     return g, name
 
 
-def bench_batch(args):
+def bench_batch(args, cpu_sample: int = 0):
     """512 planted-partition graphs (sizes log-uniform 1e3..2e5) solved in det
     mode: one batched launch sequence vs one lpa_run per graph, identical
-    labels required."""
+    labels required.  cpu_sample > 0: the cpu_baseline leg solves that many of
+    the graphs with the CPU oracle (timed) and compares their labels."""
     import hashlib
 
     import numpy as np
@@ -222,10 +268,36 @@ def bench_batch(args):
         "init_s": round(init_s, 2), "gen_s": round(gen_s, 1),
         "max_iterations": max(timings["batched_iters"]),
     }
+    if cpu_sample > 0:
+        res["cpu_baseline"] = batch_cpu_baseline(gs, solvers, args, cpu_sample)
     batch.close()
     for s in solvers:
         s.close()
-    print(json.dumps(res), flush=True)
+    return res
+
+
+def batch_cpu_baseline(gs, solvers, args, count):
+    """The oracle's whole run (all host threads) on every (512 / count)-th
+    graph of the batch: graphs/s on the host, and whether its labels and
+    iteration counts equal the batched GPU run's."""
+    import numpy as np
+    import oracle
+
+    idx = list(range(0, len(gs), max(1, len(gs) // count)))[:count]
+    t = time.perf_counter()
+    same = True
+    for i in idx:
+        g = gs[i]
+        ref, it, _, _ = oracle.lpa_run(g.row_ptr, g.col, None, k=args.k, tol=args.tol,
+                                       max_iter=args.max_iter)
+        same = same and bool(np.array_equal(ref, solvers[i].labels(device=False))
+                             and it == solvers[i].iterations())
+    dt = time.perf_counter() - t
+    return {"value": round(len(idx) / dt, 2), "unit": "graphs/s", "cores": int(oracle.max_threads()),
+            "kind": "oracle",
+            "sample": f"{len(idx)} of the {len(gs)} graphs (every {len(gs) // len(idx)}th), whole "
+                      f"det run each, {dt:.1f} s",
+            "labels_equal_gpu_batched": same}
 
 
 def bench_serve(args):
@@ -255,6 +327,7 @@ def bench_serve(args):
         f"({sum(g.nnz for g in gs)} entries)")
     be = Backend(k=args.k, mode=args.mode, tol=args.tol, max_iter=args.max_iter,
                  capacity=args.serve_slots)
+    overlap = not args.serve_no_overlap
     # sequential service: one request at a time, each solved alone
     seq_labels, seq_ms = [], []
     for _ in range(args.warmup):
@@ -284,11 +357,13 @@ def bench_serve(args):
         seq_lat = np.array(fin) - arr
         seq_span = fin[-1] - arr[0]
         # continuous batching
-        srv = Server(be, max_resident=args.serve_slots, hbm_reserve=1 << 30)
+        srv = Server(be, max_resident=args.serve_slots, hbm_reserve=1 << 30,
+                     overlap_admission=overlap)
         t0 = srv.clock()
         for g, a in zip(gs, arr):
             srv.submit(g.row_ptr, g.col, g.w, arrival=t0 + float(a))
         srv.run_until_idle()
+        srv.close()
         span = max(r.finished for r in srv.completed) - (t0 + arr[0])
         by_id = {r.rid: r for r in srv.completed}
         same = same and all(np.array_equal(by_id[i].labels, seq_labels[i]) for i in range(len(gs)))
@@ -311,7 +386,8 @@ def bench_serve(args):
         "config": {"workload": f"serve-mix{len(gs)}-{args.mode}-k{args.k}", "requests": len(gs),
                    "arrival_rate_per_s": head["arrival_rate_per_s"],
                    "load_vs_sequential": head["load_vs_sequential"],
-                   "slots": args.serve_slots, "rmat_max_scale": args.serve_max_scale},
+                   "slots": args.serve_slots, "rmat_max_scale": args.serve_max_scale,
+                   "overlapped_admission": overlap},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "sequential_graphs_per_s_capacity": round(mu_seq, 2),
         "mean_service_ms": round(float(np.mean(seq_ms)), 3),
@@ -319,7 +395,7 @@ def bench_serve(args):
         "identical_to_alone": bool(same), "gen_s": round(gen_s, 1),
     }
     be.close()
-    print(json.dumps(res), flush=True)
+    return res
 
 
 def main():
@@ -363,6 +439,11 @@ def main():
                     help="per-vertex rule: k-slot Misra-Gries sketch, or the vote of "
                          "Algorithm 3 (forces k=1)")
     ap.add_argument("--mode", default="async", choices=["async", "det"])
+    ap.add_argument("--ranked", action="store_true",
+                    help="ranked layout: labels and flags by degree-order position, column "
+                         "indices rewritten as positions (LPA_RANKED_LAYOUT, +4 B per entry)")
+    ap.add_argument("--no-other-layout", action="store_true",
+                    help="leave out the measurement of the other state layout")
     ap.add_argument("--max-iter", type=int, default=20)
     ap.add_argument("--tol", type=float, default=0.05)
     ap.add_argument("--lane-max-degree", type=int, default=0)
@@ -377,7 +458,15 @@ def main():
                     help="arrival rates as multiples of the sequential service rate; the "
                          "headline value is the heaviest")
     ap.add_argument("--serve-slots", type=int, default=32)
-    ap.add_argument("--serve-max-scale", type=int, default=18)
+    ap.add_argument("--serve-max-scale", type=int, default=20)
+    ap.add_argument("--serve-no-overlap", action="store_true",
+                    help="admit requests inside the tick loop (no admission thread and stream)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="graph workload: leave out the batched sub-measurement")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="graph workload: leave out the serving sub-measurement")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="graph workload: leave out the det-mode quality run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -410,11 +499,13 @@ def main():
     if args.workload == "batch":
         if args.mode == "async" and "--mode" not in sys.argv:
             args.mode = "det"
-        return bench_batch(args)
+        print(json.dumps(bench_batch(args, 0 if args.no_cpu_baseline else 8)), flush=True)
+        return
     if args.workload == "serve":
         if "--mode" not in sys.argv:
             args.mode = "det"
-        return bench_serve(args)
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
     dev = torch.device("cuda:0")
     if args.graph == "ring":
         from types import SimpleNamespace
@@ -437,7 +528,8 @@ def main():
     rule_tag = ((f"k{args.k}" if args.rule == "mg" else "bm-paper") + ("-rescan" if args.rescan else "")
                 + ("-hubshared" if args.hub_shared else "")
                 + ("-sharedvars" if args.shared_vars else ""))
-    workload = f"{gname}-{args.mode}-{rule_tag}" + ("-off64" if args.offsets64 else "")
+    workload = (f"{gname}-{args.mode}-{rule_tag}" + ("-off64" if args.offsets64 else "")
+                + ("-ranked" if args.ranked else ""))
 
     if args.graph != "ring":
         t = time.perf_counter()
@@ -463,11 +555,15 @@ def main():
         log(f"[bench] autotuned lane_max_degree = {args.lane_max_degree} ({tuned['table']})")
     free0, _ = torch.cuda.mem_get_info(dev)
     t = time.perf_counter()
-    solver = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
-                     mode=args.mode, lane_max_degree=args.lane_max_degree, rule=args.rule,
-                     rescan=args.rescan, hub_shared=args.hub_shared, shared_vars=args.shared_vars,
-                     stream_csr=args.stream_csr, stream_chunk_kib=args.stream_chunk_kib,
-                     check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
+    def make_solver(ranked):
+        return lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
+                       mode=args.mode, lane_max_degree=args.lane_max_degree, rule=args.rule,
+                       rescan=args.rescan, hub_shared=args.hub_shared,
+                       shared_vars=args.shared_vars, stream_csr=args.stream_csr,
+                       stream_chunk_kib=args.stream_chunk_kib, ranked=ranked,
+                       check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
+
+    solver = make_solver(args.ranked)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t) * 1e3
     free1, _ = torch.cuda.mem_get_info(dev)
@@ -475,34 +571,11 @@ def main():
     solver.profile(True)
     log(f"[bench] lpa_init {init_ms:.1f} ms; library bytes/vertex {core_bytes / g.n:.2f}")
 
-    for i in range(args.warmup):
-        solver.reset()
-        it = solver.run()
-        log(f"[bench] warmup {i}: {it} iterations")
-
-    edges_total = 0
-    kernel_bytes = 0
-    kernel_ms = 0.0
-    launches = 0
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    per_step = []
-    for s in range(args.steps):
-        ts = time.perf_counter()
-        solver.reset()
-        it = solver.run()
-        dn, sc = solver.trace()
-        ms = solver.move_ms()
-        per_step.append((time.perf_counter() - ts) * 1e3)
-        iters.append(it)
-        edges_total += int(sc.sum())
-        kernel_bytes += BYTES_PER_EDGE * int(sc.sum())
-        kernel_ms += float(ms.sum())
-        launches += len(ms)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    log(f"[bench] timed {args.steps} steps in {elapsed:.3f}s; iterations {iters}")
+    tm = timed_solves(solver, args.steps, args.warmup)
+    edges_total, elapsed, kernel_ms, launches, iters = (tm["edges"], tm["elapsed"],
+                                                        tm["kernel_ms"], tm["launches"],
+                                                        tm["iters"])
+    kernel_bytes = BYTES_PER_EDGE * edges_total
 
     floor_ms = solver.memory_floor_ms(3)
     labels = solver.labels(device=True)
@@ -540,6 +613,7 @@ def main():
                    "lane_max_degree": args.lane_max_degree or (1024 if args.mode == "async"
                                                                 else 4096),
                    "rescan": args.rescan, "offsets": 64 if args.offsets64 else 32,
+                   "ranked_layout": bool(args.ranked),
                    "mode": args.mode,
                    "tol": args.tol, "max_iter": args.max_iter, "rho": 8,
                    "step": "lpa_reset + lpa_run (all iterations to convergence)"},
@@ -579,10 +653,68 @@ def main():
                               "ns_per_entry": tuned["table"], "seconds": tuned["seconds"]}
     del labels
     solver.close()
+    if (not args.no_other_layout and args.graph != "ring"
+            and not (args.stream_csr or args.host_csr)):
+        # the same measurement with the other state layout
+        other = make_solver(not args.ranked)
+        other.profile(True)
+        tmo = timed_solves(other, args.steps, 1, tag=" [other layout]")
+        fl = other.memory_floor_ms(3)
+        ach = (BYTES_PER_EDGE * tmo["edges"] / (tmo["kernel_ms"] * 1e-3) / 1e9
+               if tmo["kernel_ms"] > 0 else 0.0)
+        cb, _ = other.memory()
+        result["other_layout"] = {
+            "ranked": not args.ranked, "value": round(tmo["edges"] / tmo["elapsed"] / 1e9, 3),
+            "unit": "GTEPS", "ms_per_step": round(tmo["elapsed"] * 1e3 / args.steps, 3),
+            "avg_launch_ms": round(tmo["kernel_ms"] / max(tmo["launches"], 1), 4),
+            "achieved_GBps": round(ach, 1), "frac": round(ach / HBM_PEAK_GBPS, 4),
+            "scan_memory_floor_ms": round(fl, 4), "iterations": tmo["iters"][-1],
+            "modularity": round(other.modularity(), 6), "bytes_per_vertex": round(cb / g.n, 3)}
+        other.close()
+    quality = (not args.no_quality and args.mode == "async" and args.rule == "mg"
+               and not (args.host_csr or args.stream_csr or args.hub_shared))
+    if quality:
+        # the same graph in det mode: Jacobi updates, every sketch fed in CSR
+        # order (the labels the CPU definition of the method gives)
+        log("[bench] det-mode run of the same graph for the quality comparison")
+        det = lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter, mode="det",
+                      rescan=args.rescan, check_every=1, stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it_det = det.run()
+        torch.cuda.synchronize()
+        det_s = time.perf_counter() - t
+        _, sc_det = det.trace()
+        result["quality"] = {
+            "q_async": round(q, 6), "async_iterations": iters[-1],
+            "q_det": round(det.modularity(), 6), "det_iterations": it_det,
+            "det_solve_ms": round(det_s * 1e3, 2),
+            "det_GTEPS": round(int(sc_det.sum()) / det_s / 1e9, 3),
+            "q_exact_oracle": None,
+            "note": "q_det: det mode on the GPU (labels bit-identical to the Misra-Gries oracle); "
+                    "q_exact_oracle: the exact rule of Eq. 3, from cpu_baseline.exact_rule_run"}
+        det.close()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a vertex sample")
         result["cpu_baseline"] = cpu_baseline(g, args.k if args.rule == "mg" else -1,
-                                              args.cpu_seconds)
+                                              args.cpu_seconds, exact_run=quality)
+        if quality:
+            result["quality"]["q_exact_oracle"] = result["cpu_baseline"]["exact_rule_run"]["q"]
+    del rp, col, w
+    torch.cuda.empty_cache()
+    import copy
+    if not args.no_batch and args.graph == "rmat" and args.scale == 24:
+        log("[bench] batched workload (512 planted-partition graphs, det, captured)")
+        ba = copy.copy(args)
+        ba.mode, ba.capture, ba.k = "det", True, 8
+        ba.steps, ba.warmup = min(args.steps, 5), 1
+        result["batch"] = bench_batch(ba, 0 if args.no_cpu_baseline else 8)
+        torch.cuda.empty_cache()
+    if not args.no_serve and args.graph == "rmat" and args.scale == 24:
+        log("[bench] serving workload (Poisson mix, continuous batching)")
+        sa = copy.copy(args)
+        sa.mode, sa.k, sa.warmup = "det", 8, 1
+        result["serve"] = bench_serve(sa)
     print(json.dumps(result), flush=True)
 
 

@@ -142,6 +142,22 @@ typedef enum lpa_status {
  * iteration; LPA_CAPTURE and lpa_batch_* do not apply (batches refuse such
  * handles with LPA_ERR_ARG). */
 #define LPA_STREAM_CSR 0x4000u
+/* Ranked layout of the device state (not with LPA_STREAM_CSR: LPA_ERR_ARG):
+ * lpa_init lists the vertices in decreasing-degree order (the order of its
+ * degree binning; isolated vertices last) and keeps each vertex's label
+ * and unprocessed flag at its position in that order instead of at its id,
+ * with a copy of col_idx rewritten as positions (int32[nnz], owned by the
+ * handle; +4 bytes per CSR entry of device memory, part of
+ * lpa_workspace_bytes).  The label values are still vertex ids, every
+ * sketch still sees its row in CSR order, and the rows are still read from
+ * the caller's row offsets and weights, so LPA_MODE_DET results are
+ * bit-identical to the default layout.  What changes is locality: the
+ * labels of the high-degree vertices, which most CSR entries name, sit
+ * together at the front of the label array, so the per-entry label reads
+ * of the neighbourhood scans hit the caches far more often, and a
+ * wavefront's own labels and flags are read contiguously.  Labels, flags
+ * and checkpoints cross the ABI indexed by vertex id as usual. */
+#define LPA_RANKED_LAYOUT 0x8000u
 
 /* Undirected graph as symmetric CSR (paper Section 3: w_ij = w_ji).  Row
  * offsets are given either as int32 (row_ptr, graphs of fewer than 2^31 - 1
@@ -162,7 +178,7 @@ typedef struct lpa_config {
   uint32_t flags;          /* LPA_MODE_DET or LPA_MODE_ASYNC,
                               | LPA_VALIDATE, | LPA_RULE_BM_PAPER, | LPA_RESCAN,
                               | LPA_HUB_SHARED, | LPA_CAPTURE, | LPA_SHARED_VARS,
-                              | LPA_STREAM_CSR */
+                              | LPA_STREAM_CSR, | LPA_RANKED_LAYOUT */
   int32_t rho;             /* pick-less period; 0 disables pick-less; default 8 */
   void *stream;            /* hipStream_t for all work; NULL = null stream */
   int32_t lane_max_degree; /* vertices with degree <= this run one lane per
@@ -225,7 +241,9 @@ int lpa_pointer_location(const void *ptr, int *location);
  *   seed     recorded only; no mode draws random numbers
  *   cfg      NULL = lpa_config_default
  * Allocates the label, flag, bin and counter arrays on the current device,
- * bins the vertices by degree, and sets labels to vertex ids.
+ * bins the vertices by degree (the degree-dependent assignment of threads to
+ * vertices of Section 4.2), and sets up the start of Algorithm 1 (lpa):
+ * every label is the vertex id and every vertex is unprocessed.
  * On success *out receives the handle; on failure *out is NULL. */
 int lpa_init(const lpa_graph *g, const float *weights, int k, double tol,
              int max_iter, uint64_t seed, const lpa_config *cfg,
@@ -240,6 +258,13 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol,
 int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter,
                         const lpa_config *cfg, size_t *bytes);
 
+/* Move the handle to another stream: synchronises the current one, then
+ * enqueues all later work of the handle on `stream` (NULL = null stream).
+ * Lets a caller build a handle on a stream of its own (lpa_init copies and
+ * bins there) while other handles keep computing, then join it to the
+ * stream of a batch.  LPA_ERR_ARG for a handle with LPA_STREAM_CSR. */
+int lpa_set_stream(lpa_handle *h, void *stream);
+
 /* Return the handle to iteration 0 (labels = ids, all vertices unprocessed,
  * traces cleared) without re-binning.  Enqueued; does not synchronise. */
 int lpa_reset(lpa_handle *h);
@@ -251,7 +276,10 @@ int lpa_reset(lpa_handle *h);
  * pointer may be NULL. */
 int lpa_step(lpa_handle *h, int64_t *changed, int *done);
 
-/* Run iterations until convergence or max_iter, then synchronise.
+/* The main loop of Algorithm 1 (lpa; Section 4.6): run iterations (one
+ * lpaMove each, pick-less every rho iterations from the first, Section 4.5)
+ * until a non-pick-less iteration changes fewer than tol * N labels or
+ * max_iter iterations have run, then synchronise.
  * *iterations (may be NULL) = total iterations run since init / reset. */
 int lpa_run(lpa_handle *h, int *iterations);
 
@@ -342,7 +370,10 @@ int lpa_profile(lpa_handle *h, int enable);
 
 /* Duration in milliseconds of the move kernel of each iteration of the
  * current run (move_ms[i] for i < *count = iterations run; at most
- * capacity written).  LPA_ERR_STATE when profiling is off.  Synchronises. */
+ * capacity written).  An iteration whose kernel was not timed (run before
+ * profiling was enabled, skipped by lpa_set_state, or run through
+ * lpa_batch_step / lpa_batch_run) reads -1.  LPA_ERR_STATE when profiling
+ * is off.  Synchronises. */
 int lpa_get_profile(lpa_handle *h, float *move_ms, int capacity, int *count);
 
 /* Memory-pattern floor of one full scan of this graph: time (ms, best of

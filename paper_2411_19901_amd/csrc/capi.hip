@@ -27,6 +27,38 @@ __global__ void k_fill_i32_iota(int32_t *C, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) C[i] = i;
 }
 
+// Ranked layout: labels start as the ids of the vertices at each position.
+__global__ void k_copy_i32(const int32_t *src, int32_t *dst, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// pos[order[p]] = p: the degree-order position of every vertex.
+__global__ void k_positions(const int32_t *order, int n, int32_t *pos) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+    pos[order[p]] = p;
+}
+
+// Column indices rewritten as positions: colr[e] = pos[col[e]].
+__global__ void k_remap_cols(const int32_t *col, int64_t nnz, const int32_t *pos, int32_t *colr) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    colr[e] = pos[col[e]];
+}
+
+// Vertex-indexed data to and from a ranked state array:
+// out[order[p]] = st[p] and st[p] = in[order[p]].
+template <class T>
+__global__ void k_unrank(const int32_t *order, const T *st, int n, T *out) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+    out[order[p]] = st[p];
+}
+template <class T>
+__global__ void k_rank(const int32_t *order, const T *in, int n, T *st) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+    st[p] = in[order[p]];
+}
+
 __global__ void k_fill_u8(uint8_t *p, size_t count, uint8_t v) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x)
@@ -78,7 +110,7 @@ __global__ void k_check_labels(const int32_t *lab, int n, int *bad) {
 // --- degree binning: histogram -> exclusive scan -> scatter ---------------
 // Stable degree binning (once per graph, or once per id range of a streamed
 // graph): vertices v0 .. v0 + n - 1 ordered by degree class (decreasing
-// degree), increasing id within a class; isolated vertices are left out.
+// degree), increasing id within a class; isolated vertices come last.
 // Block b owns the ids v0 + [b * kBinIds, (b + 1) * kBinIds).
 //   1. k_bin_count: counts[c * nblk + b] = vertices of class c in block b;
 //   2. k_scan_*: exclusive prefix sum over counts in (class, block) order,
@@ -93,17 +125,17 @@ constexpr int kBinIds = 4096;
 constexpr int kScanChunk = 4096;  // entries per block of the prefix sum
 
 __global__ void k_bin_count(int v0, int n, RowPtr rp, int lane_max, int nblk, unsigned *counts) {
-  __shared__ unsigned cnt[kClasses];
-  for (int c = threadIdx.x; c < kClasses; c += blockDim.x) cnt[c] = 0;
+  __shared__ unsigned cnt[kBinClasses];
+  for (int c = threadIdx.x; c < kBinClasses; c += blockDim.x) cnt[c] = 0;
   __syncthreads();
   const int b0 = blockIdx.x * kBinIds;
   for (int u = b0 + threadIdx.x; u < b0 + kBinIds && u < n; u += blockDim.x) {
     const int v = v0 + u;
     const int d = (int)(rp[v + 1] - rp[v]);
-    if (d > 0) atomicAdd(&cnt[degree_class(d, lane_max)], 1u);
+    atomicAdd(&cnt[degree_class(d, lane_max)], 1u);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < kClasses; c += blockDim.x)
+  for (int c = threadIdx.x; c < kBinClasses; c += blockDim.x)
     counts[(size_t)c * nblk + blockIdx.x] = cnt[c];
 }
 
@@ -148,11 +180,14 @@ __global__ void k_scan_sums(unsigned *sums, int nchunks, const unsigned *x, int 
     sums[c] = acc;
     acc += y;
   }
-  // first position of class kHubClasses (block 0) = number of hubs
+  // first position of class kHubClasses (block 0) = number of hubs; first
+  // position of the isolated class = hubs + lane vertices
   const size_t i = (size_t)kHubClasses * nblk;
   const unsigned hubs = x[i] + sums[i / kScanChunk];
+  const size_t j = (size_t)kClasses * nblk;
+  const unsigned placed = x[j] + sums[j / kScanChunk];
   totals[0] = (int)hubs;
-  totals[1] = (int)(acc - hubs);
+  totals[1] = (int)(placed - hubs);
 }
 
 __global__ void k_scan_add(unsigned *x, size_t count, const unsigned *sums) {
@@ -165,8 +200,8 @@ __global__ void k_scan_add(unsigned *x, size_t count, const unsigned *sums) {
 // turns so that lower ids are placed first.
 __global__ __launch_bounds__(256) void k_bin_place(int v0, int n, RowPtr rp, int lane_max, int nblk,
                                                    const unsigned *offsets, int32_t *order) {
-  __shared__ unsigned next[kClasses];
-  for (int c = threadIdx.x; c < kClasses; c += blockDim.x) next[c] = 0;
+  __shared__ unsigned next[kBinClasses];
+  for (int c = threadIdx.x; c < kBinClasses; c += blockDim.x) next[c] = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const unsigned long long below = (1ull << lane) - 1ull;
@@ -175,10 +210,7 @@ __global__ __launch_bounds__(256) void k_bin_place(int v0, int n, RowPtr rp, int
     const int u = b0 + r + (int)threadIdx.x;
     const int v = v0 + u;
     int cls = -1;
-    if (u < n) {
-      const int d = (int)(rp[v + 1] - rp[v]);
-      if (d > 0) cls = degree_class(d, lane_max);
-    }
+    if (u < n) cls = degree_class((int)(rp[v + 1] - rp[v]), lane_max);
     for (int w = 0; w < 4; ++w) {
       if (wid == w) {
         unsigned long long rest = __ballot(cls >= 0);
@@ -259,8 +291,9 @@ __global__ void k_batch_reset(const GraphDesc *d, int G) {
   for (int g = blockIdx.y; g < G; g += gridDim.y) {
     const GraphDesc &gd = d[g];
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < gd.n; i += gridDim.x * blockDim.x) {
-      gd.C[0][i] = i;
-      if (gd.C[1] != gd.C[0]) gd.C[1][i] = i;
+      const int c = gd.ranked ? gd.order[i] : i;  // the id of the vertex whose label this is
+      gd.C[0][i] = c;
+      if (gd.C[1] != gd.C[0]) gd.C[1][i] = c;
       gd.act[0][i] = 1;
       if (gd.act[1] != gd.act[0]) gd.act[1][i] = 0;
     }
@@ -360,7 +393,7 @@ struct lpa_batch {
   GraphDesc *d_desc = nullptr;
   int32_t *d_prefix = nullptr;  // items, hubs, merge items, hub segments: [cap+1] each
   int32_t *d_finished = nullptr;
-  int32_t *d_status = nullptr;  // [2 * cap]
+  int32_t *d_status = nullptr;  // [3 * cap]: iter, done, dN of the last launched iteration
   void *hblock = nullptr;  // pinned host mirror of the same layout
   GraphDesc *h_desc = nullptr;
   int32_t *h_prefix = nullptr;
@@ -399,10 +432,15 @@ struct lpa_handle {
   GraphStatus *st = nullptr;
   uint32_t *hist = nullptr;  // binning scratch
   int32_t seg_cap = 0, hub_cap = 0;
+  int32_t n_segs = 0;  // hub segments planned (det mode too, for modularity)
   double *mod_tot = nullptr;
   int mod_grid = 0;  // k_modularity workgroups (resident on every CU)
   double *mod_acc = nullptr;
   std::vector<void *> eval_allocs;
+  // LPA_RANKED_LAYOUT: neighbour positions (desc.col points here) and a
+  // transfer buffer for host copies of ranked state
+  int32_t *colr = nullptr;
+  void *tmp = nullptr;
 
   int iter = 0;  // iterations run (host mirror of st->iter)
   bool finished = false;
@@ -410,6 +448,7 @@ struct lpa_handle {
   bool poisoned = false;
   std::string err;
   std::vector<hipEvent_t> ev_beg, ev_end;
+  std::vector<uint8_t> ev_rec;  // 1: the events of iteration i were recorded in this run
   lpa_batch *self = nullptr;  // batch of one used by lpa_step / lpa_run
 
   // LPA_STREAM_CSR: the graph stays in pinned host memory; every iteration
@@ -529,7 +568,8 @@ int check_k(int k, uint32_t flags) {
   if ((flags & LPA_SHARED_VARS) &&
       ((flags & LPA_MODE_MASK) != LPA_MODE_DET || (flags & (LPA_RULE_BM_PAPER | LPA_RESCAN))))
     return LPA_ERR_ARG;
-  if ((flags & LPA_STREAM_CSR) && (flags & LPA_HUB_SHARED)) return LPA_ERR_ARG;
+  if ((flags & LPA_STREAM_CSR) && (flags & (LPA_HUB_SHARED | LPA_RANKED_LAYOUT)))
+    return LPA_ERR_ARG;
   return LPA_OK;
 }
 
@@ -554,7 +594,7 @@ uint8_t *cur_flags(const lpa_handle *h) { return h->desc.act[h->iter & 1]; }
 // --- one device block per handle -------------------------------------------
 struct Layout {
   size_t st, dN, scanned, C0, C1, act0, act1, order, hist, hub_pbase, hub_act, seg_hub, pkey,
-      pval, hcand, total;
+      pval, hcand, colr, tmp, total;
   int32_t hub_cap, seg_cap, ncls;
   bool too_many_segs;
 };
@@ -565,7 +605,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // number of hub segments (a caller workspace); otherwise lpa_init sizes them
 // once the segments are planned.
 Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode, int lane_max,
-                   bool rescan, bool bound_partials) {
+                   bool rescan, bool bound_partials, bool ranked) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -574,9 +614,9 @@ Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode,
     return at;
   };
   const size_t T = (size_t)(max_iter > 0 ? max_iter : 1);
-  L.ncls = kClasses;
+  L.ncls = kBinClasses;
   const size_t nblk = ((size_t)n + kBinIds - 1) / kBinIds;
-  const size_t cells = (size_t)kClasses * (nblk ? nblk : 1);
+  const size_t cells = (size_t)kBinClasses * (nblk ? nblk : 1);
   const size_t chunks = (cells + kScanChunk - 1) / kScanChunk;
   L.st = take(sizeof(GraphStatus));
   L.dN = take(T * 8);
@@ -588,20 +628,28 @@ Layout plan_layout(int32_t n, int64_t nnz, int k, int max_iter, bool async_mode,
   L.act1 = async_mode ? L.act0 : take((size_t)n);
   L.order = take((size_t)n * 4);
   L.hist = take(chunks * 4);
-  if (async_mode) {
-    // hubs have more than S entries each; a hub of degree d > S has
-    // ceil(d / S) < 2 d / S segments
-    const int64_t hubs = nnz / (lane_max + 1) + 1;
-    const int64_t segs = 2 * (nnz / lane_max) + 2;
-    L.hub_cap = (int32_t)(hubs < n ? hubs : n);
-    if (segs >= kMaxSegs) {  // work items of one iteration must fit int32
+  if (ranked) {  // LPA_RANKED_LAYOUT: column indices as positions, a transfer buffer
+    L.colr = take((size_t)nnz * 4);
+    L.tmp = take((size_t)n * 4);
+  }
+  // hubs have more than S entries each; a hub of degree d > S has
+  // ceil(d / S) < 2 d / S segments.  Async mode scans the segments as work
+  // items; both modes spread modularity's reads of a hub over them.
+  const int64_t hubs = nnz / (lane_max + 1) + 1;
+  const int64_t segs = 2 * (nnz / lane_max) + 2;
+  if (segs >= kMaxSegs) {  // work items of one iteration must fit int32
+    if (async_mode) {
       L.too_many_segs = true;
       return L;
     }
+  } else {
+    L.hub_cap = (int32_t)(hubs < n ? hubs : n);
     L.seg_cap = (int32_t)segs;
     L.hub_pbase = take(((size_t)L.hub_cap + 1) * 4);
-    L.hub_act = take((size_t)L.hub_cap);
     L.seg_hub = take((size_t)L.seg_cap * 4);
+  }
+  if (async_mode) {
+    L.hub_act = take((size_t)L.hub_cap);
     L.pkey = take(bound_partials ? (size_t)L.seg_cap * k * 4 : 0);
     L.pval = take(bound_partials ? (size_t)L.seg_cap * k * 4 : 0);
     L.hcand = take(rescan ? (size_t)L.hub_cap * k * 4 : 0);  // double-scan candidates
@@ -615,11 +663,15 @@ int enqueue_reset(lpa_handle *h) {
   const int n = h->n;
   const size_t T = (size_t)(h->max_iter > 0 ? h->max_iter : 1);
   if (n > 0) {
-    hipLaunchKernelGGL(k_fill_i32_iota, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
-                       h->desc.C[0], n);
-    if (h->desc.C[1] != h->desc.C[0])
-      hipLaunchKernelGGL(k_fill_i32_iota, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
-                         h->desc.C[1], n);
+    for (int b = 0; b < 2; ++b) {
+      if (b == 1 && h->desc.C[1] == h->desc.C[0]) break;
+      if (h->desc.ranked)  // label at position p: the id of the vertex there
+        hipLaunchKernelGGL(k_copy_i32, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                           h->desc.order, h->desc.C[b], n);
+      else
+        hipLaunchKernelGGL(k_fill_i32_iota, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                           h->desc.C[b], n);
+    }
     hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->desc.act[0],
                        (size_t)n, (uint8_t)1);
     if (h->desc.act[1] != h->desc.act[0])
@@ -634,6 +686,56 @@ int enqueue_reset(lpa_handle *h) {
   LAUNCH_TRY(h, "reset kernels");
   h->iter = 0;
   h->finished = done0;
+  std::fill(h->ev_rec.begin(), h->ev_rec.end(), (uint8_t)0);
+  return LPA_OK;
+}
+
+// Copy the n-item state array `st` (labels: elem 4, flags: elem 1) to the
+// caller's vertex-indexed `out` (host or device), and back (state_in),
+// reordering through the degree order when the handle's state is ranked
+// (host data then passes through the transfer buffer).  Enqueued on the
+// handle's stream.
+int state_out(lpa_handle *h, const void *st, void *out, size_t elem, bool out_is_host) {
+  const int n = h->n;
+  if (!h->desc.ranked) {
+    HIP_TRY(h, hipMemcpyAsync(out, st, (size_t)n * elem,
+                              out_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                              h->stream));
+    return LPA_OK;
+  }
+  void *dst = out_is_host ? h->tmp : out;
+  if (elem == 4)
+    hipLaunchKernelGGL(k_unrank<int32_t>, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                       h->desc.order, (const int32_t *)st, n, (int32_t *)dst);
+  else
+    hipLaunchKernelGGL(k_unrank<uint8_t>, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                       h->desc.order, (const uint8_t *)st, n, (uint8_t *)dst);
+  LAUNCH_TRY(h, "state reorder");
+  if (out_is_host)
+    HIP_TRY(h, hipMemcpyAsync(out, h->tmp, (size_t)n * elem, hipMemcpyDeviceToHost, h->stream));
+  return LPA_OK;
+}
+
+int state_in(lpa_handle *h, const void *in, void *st, size_t elem, bool in_is_host) {
+  const int n = h->n;
+  if (!h->desc.ranked) {
+    HIP_TRY(h, hipMemcpyAsync(st, in, (size_t)n * elem,
+                              in_is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                              h->stream));
+    return LPA_OK;
+  }
+  const void *src = in;
+  if (in_is_host) {
+    HIP_TRY(h, hipMemcpyAsync(h->tmp, in, (size_t)n * elem, hipMemcpyHostToDevice, h->stream));
+    src = h->tmp;
+  }
+  if (elem == 4)
+    hipLaunchKernelGGL(k_rank<int32_t>, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                       h->desc.order, (const int32_t *)src, n, (int32_t *)st);
+  else
+    hipLaunchKernelGGL(k_rank<uint8_t>, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
+                       h->desc.order, (const uint8_t *)src, n, (uint8_t *)st);
+  LAUNCH_TRY(h, "state reorder");
   return LPA_OK;
 }
 
@@ -647,7 +749,7 @@ int batch_alloc(lpa_batch *b) {
   b->off_finished = off;
   off = align_up(off + sizeof(int32_t));
   b->off_status = off;
-  off = align_up(off + 2 * cap * sizeof(int32_t));
+  off = align_up(off + 3 * cap * sizeof(int32_t));
   b->block_bytes = off;
   if (hipMalloc(&b->dblock, off) != hipSuccess) {
     (void)hipGetLastError();
@@ -769,7 +871,7 @@ Launch make_launch(lpa_batch *b) {
 int batch_read_status(lpa_batch *b) {
   const int G = (int)b->loaded.size();
   if (G > 0)
-    HIP_TRY_B(b, hipMemcpyAsync(b->h_status, b->d_status, 2 * (size_t)G * sizeof(int32_t),
+    HIP_TRY_B(b, hipMemcpyAsync(b->h_status, b->d_status, 3 * (size_t)G * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, b->stream));
   HIP_TRY_B(b, hipMemcpyAsync(b->h_finished, b->d_finished, sizeof(int32_t), hipMemcpyDeviceToHost,
                               b->stream));
@@ -777,8 +879,8 @@ int batch_read_status(lpa_batch *b) {
   for (int g = 0; g < G; ++g) {
     lpa_handle *h = b->loaded[g];
     if (h->finished) continue;
-    h->iter = b->h_status[2 * g];
-    h->finished = b->h_status[2 * g + 1] != 0;
+    h->iter = b->h_status[3 * g];
+    h->finished = b->h_status[3 * g + 1] != 0;
   }
   return LPA_OK;
 }
@@ -835,6 +937,7 @@ int batch_iterate(lpa_batch *b, int iters, lpa_handle *prof) {
       if (l < (int)prof->ev_beg.size()) {
         eb = prof->ev_beg[l];
         ee = prof->ev_end[l];
+        prof->ev_rec[l] = 1;
       }
     }
     hipError_t e =
@@ -912,7 +1015,7 @@ static int check_config(const lpa_config &cfg) {
   if (mode != LPA_MODE_DET && mode != LPA_MODE_ASYNC) return LPA_ERR_UNSUPPORTED;
   if ((cfg.flags &
        ~(LPA_MODE_MASK | LPA_VALIDATE | LPA_RULE_BM_PAPER | LPA_RESCAN | LPA_HUB_SHARED |
-         LPA_CAPTURE | LPA_SHARED_VARS | LPA_STREAM_CSR)) != 0)
+         LPA_CAPTURE | LPA_SHARED_VARS | LPA_STREAM_CSR | LPA_RANKED_LAYOUT)) != 0)
     return LPA_ERR_UNSUPPORTED;
   if (cfg.workspace_bytes && !cfg.workspace) return LPA_ERR_ARG;
   return LPA_OK;
@@ -933,7 +1036,8 @@ int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter, const lpa_c
   const bool async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   const int lane_max = cfg.lane_max_degree > 0 ? cfg.lane_max_degree : default_lane_max(async_mode);
   const Layout Ly = plan_layout(n, nnz, k, max_iter, async_mode, lane_max,
-                                (cfg.flags & LPA_RESCAN) != 0, true);
+                                (cfg.flags & LPA_RESCAN) != 0, true,
+                                (cfg.flags & LPA_RANKED_LAYOUT) != 0);
   if (Ly.too_many_segs) return LPA_ERR_UNSUPPORTED;
   *bytes = Ly.total;
   return LPA_OK;
@@ -941,15 +1045,15 @@ int lpa_workspace_bytes(int32_t n, int64_t nnz, int k, int max_iter, const lpa_c
 
 namespace {
 
-// Degree-bin the vertices [v0, v0 + nr) into order[0 .. hubs + lanes): the
-// binning kernels above, with the label buffer C[0] as their count matrix
+// Degree-bin the vertices [v0, v0 + nr) into order[0 .. nr) (hubs, lane
+// vertices, then the isolated ones): the binning kernels above, with the label buffer C[0] as their count matrix
 // (before the labels are initialised) and synchronising once for the
 // totals.
 hipError_t bin_range(lpa_handle *h, int v0, int nr, int32_t *order, int *hubs, int *lanes) {
   *hubs = *lanes = 0;
   if (nr <= 0) return hipSuccess;
   const int nblk = (nr + kBinIds - 1) / kBinIds;
-  const size_t cells = (size_t)kClasses * nblk;
+  const size_t cells = (size_t)kBinClasses * nblk;
   const int nchunks = (int)((cells + kScanChunk - 1) / kScanChunk);
   unsigned *counts = (unsigned *)h->desc.C[0];
   hipLaunchKernelGGL(k_bin_count, dim3(nblk), dim3(256), 0, h->stream, v0, nr, h->row_ptr,
@@ -1203,7 +1307,10 @@ int stream_iterate(lpa_handle *h, int iters) {
   for (int i = 0; i < iters && !h->finished; ++i) {
     const int l = h->iter;
     const bool prof = !h->ev_beg.empty() && l < (int)h->ev_beg.size();
-    if (prof) HIP_TRY(h, hipEventRecord(h->ev_beg[l], h->stream));
+    if (prof) {
+      HIP_TRY(h, hipEventRecord(h->ev_beg[l], h->stream));
+      h->ev_rec[l] = 1;
+    }
     HIP_TRY(h, hipEventRecord(S.start, h->stream));
     for (int c = 1; c < NB; ++c) HIP_TRY(h, hipStreamWaitEvent(S.cs[c], S.start, 0));
     for (size_t p = 0; p < S.base.size(); ++p) {
@@ -1319,8 +1426,9 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   // one block for every array of the handle: the caller's workspace or ours
   const int n = h->n;
   const bool bound_partials = cfg.workspace != nullptr;
+  const bool ranked = (cfg.flags & LPA_RANKED_LAYOUT) != 0;
   const Layout Ly = plan_layout(n, h->nnz, k, max_iter, h->async_mode, h->lane_max,
-                                (cfg.flags & LPA_RESCAN) != 0, bound_partials);
+                                (cfg.flags & LPA_RESCAN) != 0, bound_partials, ranked);
   if (Ly.too_many_segs) return bail(set_err(h, LPA_ERR_UNSUPPORTED, "too many hub segments"));
   if (cfg.workspace) {
     if (cfg.workspace_bytes < Ly.total || ((uintptr_t)cfg.workspace & 255) != 0)
@@ -1357,12 +1465,14 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   d.dN = (unsigned long long *)(base + Ly.dN);
   d.scanned = (unsigned long long *)(base + Ly.scanned);
   d.st = h->st;
-  if (h->async_mode) {
-    h->hub_cap = Ly.hub_cap;
-    h->seg_cap = Ly.seg_cap;
+  h->hub_cap = Ly.hub_cap;
+  h->seg_cap = Ly.seg_cap;
+  if (Ly.seg_cap > 0) {
     d.hub_pbase = (const int32_t *)(base + Ly.hub_pbase);
-    d.hub_act = (uint8_t *)(base + Ly.hub_act);
     d.seg_hub = (const int32_t *)(base + Ly.seg_hub);
+  }
+  if (h->async_mode) {
+    d.hub_act = (uint8_t *)(base + Ly.hub_act);
     d.part_key = (int32_t *)(base + Ly.pkey);
     d.part_val = (float *)(base + Ly.pval);
     d.hub_cand = (int32_t *)(base + Ly.hcand);
@@ -1391,8 +1501,9 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     d.n_hubs = hubs;
     d.n_lane = lanes;
   }
-  // async: split every hub into segments of lane_max entries
-  if (h->async_mode && d.n_hubs > 0) {
+  // split every hub into segments of lane_max entries (async: the move
+  // kernels' work items; both modes: modularity's)
+  if (d.n_hubs > 0 && h->seg_cap > 0) {
     if (d.n_hubs > h->hub_cap) return bail(set_err(h, LPA_ERR_GRAPH, "hub bound violated"));
     hipLaunchKernelGGL(k_hub_plan, dim3(1), dim3(1024), 0, h->stream, d.order, d.n_hubs,
                        h->row_ptr, h->lane_max, (int32_t *)d.hub_pbase, &h->st->totals[2]);
@@ -1403,11 +1514,12 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
         hipStreamSynchronize(h->stream) != hipSuccess)
       return bail(LPA_ERR_HIP);
     if (nseg > h->seg_cap) return bail(set_err(h, LPA_ERR_GRAPH, "segment bound violated"));
-    d.n_seg = nseg;
+    h->n_segs = nseg;
+    if (h->async_mode) d.n_seg = nseg;  // det mode scans whole hub rows
     hipLaunchKernelGGL(k_fill_seg_hub, dim3(grid_for(d.n_hubs)), dim3(kAuxBlock), 0, h->stream,
                        d.hub_pbase, d.n_hubs, (int32_t *)d.seg_hub);
     if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
-    if (!bound_partials && !streamed && nseg > 0) {  // partial sketches for exactly nseg
+    if (h->async_mode && !bound_partials && !streamed && nseg > 0) {  // partial sketches for exactly nseg
       const size_t half = align_up((size_t)nseg * k * 4);
       if (hipMalloc(&h->part_block, 2 * half) != hipSuccess) {
         (void)hipGetLastError();
@@ -1417,6 +1529,21 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
       d.part_key = (int32_t *)h->part_block;
       d.part_val = (float *)((char *)h->part_block + half);
     }
+  }
+  // ranked layout: every vertex's state moves to its degree-order position,
+  // and the column indices are rewritten as positions (C[0] holds the
+  // positions meanwhile; the reset below sets the labels)
+  if (ranked && n > 0) {
+    h->colr = (int32_t *)(base + Ly.colr);
+    h->tmp = base + Ly.tmp;
+    hipLaunchKernelGGL(k_positions, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, d.order, n,
+                       d.C[0]);
+    if (h->nnz > 0)
+      hipLaunchKernelGGL(k_remap_cols, dim3(grid_for((size_t)h->nnz, kAuxBlock, 8192)),
+                         dim3(kAuxBlock), 0, h->stream, h->col, h->nnz, d.C[0], h->colr);
+    if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
+    d.col = h->colr;
+    d.ranked = 1;
   }
   d.hub_shared = (cfg.flags & LPA_HUB_SHARED) ? 1 : 0;
   d.items = h->async_mode ? ((d.hub_shared ? 0 : d.n_seg) + d.n_lane + kWave - 1) / kWave
@@ -1439,6 +1566,16 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   if ((rc = enqueue_reset(h)) != LPA_OK) return bail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LPA_ERR_HIP);
   *out = h;
+  return LPA_OK;
+}
+
+int lpa_set_stream(lpa_handle *h, void *stream) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (h->sm.on) return set_err(h, LPA_ERR_ARG, "a streamed CSR keeps the streams of lpa_init");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->stream = (hipStream_t)stream;
+  h->self->stream = h->stream;
   return LPA_OK;
 }
 
@@ -1553,18 +1690,16 @@ int lpa_batch_step(lpa_batch *b, lpa_handle *const *hs, int count, int64_t *chan
   if (b->poisoned) return LPA_ERR_HIP;
   int rc = batch_load(b, hs, count);
   if (rc) return batch_error_to_handles(b, rc);
-  std::vector<int> before(count);
-  for (int g = 0; g < count; ++g) before[g] = hs[g]->finished ? -1 : hs[g]->iter;
+  std::vector<char> ran(count);
+  for (int g = 0; g < count; ++g) ran[g] = !hs[g]->finished;
   if ((rc = batch_iterate(b, 1, nullptr)) != LPA_OK) return batch_error_to_handles(b, rc);
+  // the stop test wrote every graph's iteration, status and dN into the
+  // status table, which this reads back with one copy
   if ((rc = batch_read_status(b)) != LPA_OK) return batch_error_to_handles(b, rc);
   int64_t total = 0;
   bool all = true;
   for (int g = 0; g < count; ++g) {
-    if (before[g] >= 0) {
-      unsigned long long dn = 0;
-      HIP_TRY_B(b, hipMemcpy(&dn, hs[g]->desc.dN + before[g], sizeof(dn), hipMemcpyDeviceToHost));
-      total += (int64_t)dn;
-    }
+    if (ran[g]) total += (int64_t)b->h_status[3 * g + 2];
     all = all && hs[g]->finished;
   }
   if (changed) *changed = total;
@@ -1590,10 +1725,8 @@ int lpa_get_labels(lpa_handle *h, int32_t *out, int out_is_host) {
   int rc = check_ready(h);
   if (rc) return rc;
   if (!out && h->n > 0) return LPA_ERR_ARG;
-  if (h->n > 0)
-    HIP_TRY(h, hipMemcpyAsync(out, cur_labels(h), (size_t)h->n * sizeof(int32_t),
-                              out_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                              h->stream));
+  if (h->n > 0 && (rc = state_out(h, cur_labels(h), out, sizeof(int32_t), out_is_host)) != LPA_OK)
+    return rc;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return LPA_OK;
 }
@@ -1622,6 +1755,70 @@ int lpa_get_trace(lpa_handle *h, int64_t *changed, int64_t *scanned, int capacit
   return LPA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Modularity of `labels` (NULL: the handle's current labels) with the
+// community totals in tot[0, n) (all zero on entry; left zero) and the four
+// fp64 accumulators in acc.
+int modularity_into(lpa_handle *h, const int32_t *labels, double *q, double *tot, double *acc) {
+  const int n = h->n;
+  if (labels && pointer_location(labels) == LPA_PTR_UNUSABLE)
+    return set_err(h, LPA_ERR_ARG, "labels must be device or mapped pinned host memory");
+  const int32_t *lab = labels ? labels : cur_labels(h);
+  const GraphDesc &d = h->desc;
+  hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
+  if (labels) {  // the library's own labels are in range by construction
+    hipLaunchKernelGGL(k_check_labels, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, labels, n,
+                       &h->st->err);
+    LAUNCH_TRY(h, "label check");
+    int bad = 0;
+    HIP_TRY(h, hipMemcpyAsync(&bad, &h->st->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (bad) {
+      hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
+      LAUNCH_TRY(h, "label check reset");
+      return set_err(h, LPA_ERR_GRAPH, "label out of range [0, n)");
+    }
+  }
+  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, h->stream, acc, 4);
+  ModArgs m;
+  m.order = d.order;
+  m.n_hubs = d.n_hubs;
+  m.n_lane = d.n_lane;
+  // hubs are read segment by segment (one wavefront per segment) when the
+  // handle planned its segments; otherwise one wavefront per hub
+  m.n_seg = h->sm.on ? 0 : h->n_segs;
+  m.seg_len = h->lane_max;
+  m.seg_hub = d.seg_hub;
+  m.hub_pbase = d.hub_pbase;
+  m.row_ptr = h->row_ptr;
+  // the handle's own labels are stored ranked with a ranked layout; a
+  // caller's labels are indexed by vertex id
+  m.ranked = labels ? 0 : d.ranked;
+  m.col = labels ? h->col : d.col;
+  m.w = h->w;
+  m.lab = lab;
+  m.tot = tot;
+  m.acc = acc;
+  if (h->mod_grid == 0) h->mod_grid = h->self->cus * modularity_blocks_per_cu();
+  HIP_TRY(h, launch_modularity(m, h->mod_grid, h->stream));
+  hipLaunchKernelGGL(k_mod_sq, dim3(grid_for(n, kAuxBlock, 4096)), dim3(kAuxBlock), 0, h->stream,
+                     tot, n, acc);
+  LAUNCH_TRY(h, "modularity kernels");
+  double out[4] = {0, 0, 0, 0};
+  HIP_TRY(h, hipMemcpyAsync(out, acc, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  const double two_m = out[0];
+  *q = two_m > 0.0 ? out[1] / two_m - out[2] / (two_m * two_m) : 0.0;
+  return LPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q) {
   int rc = check_ready(h);
   if (rc) return rc;
@@ -1643,46 +1840,7 @@ int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q) {
     h->mod_acc = (double *)((char *)p + align_up((size_t)n * sizeof(double)));
     hipLaunchKernelGGL(k_zero_d, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->mod_tot, n);
   }
-  if (labels && pointer_location(labels) == LPA_PTR_UNUSABLE)
-    return set_err(h, LPA_ERR_ARG, "labels must be device or mapped pinned host memory");
-  const int32_t *lab = labels ? labels : cur_labels(h);
-  const GraphDesc &d = h->desc;
-  hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
-  if (labels) {  // the library's own labels are in range by construction
-    hipLaunchKernelGGL(k_check_labels, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, labels, n,
-                       &h->st->err);
-    LAUNCH_TRY(h, "label check");
-    int bad = 0;
-    HIP_TRY(h, hipMemcpyAsync(&bad, &h->st->err, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(h, hipStreamSynchronize(h->stream));
-    if (bad) {
-      hipLaunchKernelGGL(k_status_clear_err, dim3(1), dim3(64), 0, h->stream, h->st);
-      LAUNCH_TRY(h, "label check reset");
-      return set_err(h, LPA_ERR_GRAPH, "label out of range [0, n)");
-    }
-  }
-  hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(64), 0, h->stream, h->mod_acc, 4);
-  ModArgs m;
-  m.order = d.order;
-  m.n_hubs = d.n_hubs;
-  m.n_lane = d.n_lane;
-  m.row_ptr = h->row_ptr;
-  m.col = h->col;
-  m.w = h->w;
-  m.lab = lab;
-  m.tot = h->mod_tot;
-  m.acc = h->mod_acc;
-  if (h->mod_grid == 0) h->mod_grid = h->self->cus * modularity_blocks_per_cu();
-  HIP_TRY(h, launch_modularity(m, h->mod_grid, h->stream));
-  hipLaunchKernelGGL(k_mod_sq, dim3(grid_for(n, kAuxBlock, 4096)), dim3(kAuxBlock), 0, h->stream,
-                     h->mod_tot, n, h->mod_acc);
-  LAUNCH_TRY(h, "modularity kernels");
-  double acc[4] = {0, 0, 0, 0};
-  HIP_TRY(h, hipMemcpyAsync(acc, h->mod_acc, sizeof(acc), hipMemcpyDeviceToHost, h->stream));
-  HIP_TRY(h, hipStreamSynchronize(h->stream));
-  const double two_m = acc[0];
-  *q = two_m > 0.0 ? acc[1] / two_m - acc[2] / (two_m * two_m) : 0.0;
-  return LPA_OK;
+  return modularity_into(h, labels, q, h->mod_tot, h->mod_acc);
 }
 
 int lpa_get_state(lpa_handle *h, int32_t *labels, uint8_t *unprocessed, int *iteration,
@@ -1690,11 +1848,11 @@ int lpa_get_state(lpa_handle *h, int32_t *labels, uint8_t *unprocessed, int *ite
   int rc = check_ready(h);
   if (rc) return rc;
   const int n = h->n;
-  const hipMemcpyKind kind = is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  if (n > 0 && labels)
-    HIP_TRY(h, hipMemcpyAsync(labels, cur_labels(h), (size_t)n * sizeof(int32_t), kind, h->stream));
-  if (n > 0 && unprocessed)
-    HIP_TRY(h, hipMemcpyAsync(unprocessed, cur_flags(h), (size_t)n, kind, h->stream));
+  if (n > 0 && labels &&
+      (rc = state_out(h, cur_labels(h), labels, sizeof(int32_t), is_host)) != LPA_OK)
+    return rc;
+  if (n > 0 && unprocessed && (rc = state_out(h, cur_flags(h), unprocessed, 1, is_host)) != LPA_OK)
+    return rc;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   if (iteration) *iteration = h->iter;
   return LPA_OK;
@@ -1727,12 +1885,12 @@ int lpa_set_state(lpa_handle *h, const int32_t *labels, const uint8_t *unprocess
   if ((rc = enqueue_reset(h)) != LPA_OK) return rc;
   const GraphDesc &d = h->desc;
   if (n > 0) {
-    const hipMemcpyKind kind = is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
     uint8_t *cur = d.act[iteration & 1];
-    HIP_TRY(h, hipMemcpyAsync(d.C[0], labels, (size_t)n * sizeof(int32_t), kind, h->stream));
+    if ((rc = state_in(h, labels, d.C[0], sizeof(int32_t), is_host)) != LPA_OK) return rc;
     if (d.C[1] != d.C[0])  // both buffers: vertices of degree 0 are never rewritten
-      HIP_TRY(h, hipMemcpyAsync(d.C[1], labels, (size_t)n * sizeof(int32_t), kind, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(cur, unprocessed, (size_t)n, kind, h->stream));
+      HIP_TRY(h, hipMemcpyAsync(d.C[1], d.C[0], (size_t)n * sizeof(int32_t),
+                                hipMemcpyDeviceToDevice, h->stream));
+    if ((rc = state_in(h, unprocessed, cur, 1, is_host)) != LPA_OK) return rc;
     hipLaunchKernelGGL(k_normalize_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, cur, n);
     if (d.act[1] != d.act[0])
       hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream,
@@ -1756,10 +1914,12 @@ int lpa_profile(lpa_handle *h, int enable) {
   for (hipEvent_t e : h->ev_end) (void)hipEventDestroy(e);
   h->ev_beg.clear();
   h->ev_end.clear();
+  h->ev_rec.clear();
   if (enable) {
     const int T = h->max_iter > 0 ? h->max_iter : 1;
     h->ev_beg.resize(T);
     h->ev_end.resize(T);
+    h->ev_rec.assign(T, 0);
     for (int i = 0; i < T; ++i) {
       HIP_TRY(h, hipEventCreate(&h->ev_beg[i]));
       HIP_TRY(h, hipEventCreate(&h->ev_end[i]));
@@ -1775,8 +1935,13 @@ int lpa_get_profile(lpa_handle *h, float *move_ms, int capacity, int *count) {
   if (capacity < 0) return LPA_ERR_ARG;
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   const int cnt = h->iter;
+  // iterations run before profiling was enabled, restored by lpa_set_state
+  // or run through a batch have no events: -1
   for (int i = 0; i < cnt && i < capacity && move_ms; ++i)
-    HIP_TRY(h, hipEventElapsedTime(&move_ms[i], h->ev_beg[i], h->ev_end[i]));
+    move_ms[i] = -1.0f;
+  for (int i = 0; i < cnt && i < capacity && move_ms; ++i)
+    if (i < (int)h->ev_rec.size() && h->ev_rec[i])
+      HIP_TRY(h, hipEventElapsedTime(&move_ms[i], h->ev_beg[i], h->ev_end[i]));
   if (count) *count = cnt;
   return LPA_OK;
 }
@@ -1793,7 +1958,7 @@ int lpa_memory_floor(lpa_handle *h, int reps, float *ms) {
   float best = -1.0f;
   for (int r = 0; r < reps + 1; ++r) {  // the first launch warms the caches
     HIP_TRY(h, hipEventRecord(b, h->stream));
-    hipLaunchKernelGGL(k_scan_floor, dim3(4096), dim3(kAuxBlock), 0, h->stream, h->col, h->w,
+    hipLaunchKernelGGL(k_scan_floor, dim3(4096), dim3(kAuxBlock), 0, h->stream, h->desc.col, h->w,
                        (const int32_t *)cur_labels(h), h->nnz, &h->st->sink);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(e, h->stream));

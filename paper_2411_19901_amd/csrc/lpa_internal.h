@@ -24,6 +24,10 @@ constexpr int kHubClasses = 256;
 constexpr int kLaneBuckets = 88;  // eighth-octave buckets for degrees 65 .. 2^17 - 1
 constexpr int kLaneExact = 64;    // one class per degree 1 .. 64
 constexpr int kClasses = kHubClasses + kLaneBuckets + kLaneExact;
+// The binning adds one class after these for the isolated vertices (degree
+// 0), so that the degree order lists every vertex: hubs, lane vertices,
+// then isolated ones.
+constexpr int kBinClasses = kClasses + 1;
 
 __host__ __device__ inline int octave_bucket(int d) {  // d >= 1
   const int b = 31 - __builtin_clz((unsigned)d);
@@ -32,6 +36,7 @@ __host__ __device__ inline int octave_bucket(int d) {  // d >= 1
 }
 
 __host__ __device__ inline int degree_class(int d, int lane_max) {
+  if (d == 0) return kClasses;  // isolated: last
   if (d > lane_max) return kHubClasses - 1 - octave_bucket(d);
   if (d > kLaneExact) return kHubClasses + kLaneBuckets - 1 - (octave_bucket(d) - 6 * 8);
   return kHubClasses + kLaneBuckets + (kLaneExact - d);
@@ -83,8 +88,12 @@ struct GraphDesc {
   int32_t items;      // move-kernel work items per iteration
   double tol;
   RowPtr row_ptr;
-  const int32_t *col;
+  const int32_t *col;  // neighbour ids; with `ranked`, their degree-order positions
   const float *w;     // nullable: unit weights
+  // 1: labels and flags are stored by degree-order position (the vertex at
+  // order[p] keeps its state at index p) and `col` holds positions; the
+  // label values are vertex ids either way
+  int32_t ranked;
   int32_t *C[2];      // det: labels of even / odd iterations; async: both C[0]
   uint8_t *act[2];    // det: flags of even / odd iterations; async: both act[0]
   const int32_t *order;      // vertex ids: hubs (desc degree), then lane vertices
@@ -115,7 +124,7 @@ struct Launch {
   int32_t total_merge;
   int32_t total_segs;
   int32_t *finished;        // graphs that have finished (counter)
-  int32_t *status_out;      // [2 * G]: iter, done of every graph after the launch
+  int32_t *status_out;      // [3 * G]: iter, done, dN of the iteration just run (0: none)
   int32_t no_finish;        // 1: launch_iteration leaves out the stop test (k_finish)
 };
 
@@ -130,6 +139,7 @@ struct MoveArgs {
   gptr<uint8_t> act_cur;   // unprocessed flags read (and cleared) this iteration
   gptr<uint8_t> act_next;  // flags set for the next iteration (async: == act_cur)
   gptr<const int32_t> order;
+  int32_t ranked;          // state indexed by degree-order position (GraphDesc::ranked)
   int32_t n_hubs;
   int32_t n_lane;
   int32_t seg_len;
@@ -165,7 +175,8 @@ int move_blocks_per_cu(int k, bool async_mode, bool rescan, bool shared_vars, bo
 hipError_t launch_finish(const Launch &L, hipStream_t s);
 
 // Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read
-// by one wavefront each, order[n_hubs, n_hubs + n_lane) one lane each.
+// by one wavefront per segment (or per hub without segments),
+// order[n_hubs, n_hubs + n_lane) one lane each.
 // Labels must lie in [0, n).  acc[0] += 2m, acc[1] += sigma,
 // tot[c] += K_i for every vertex i labelled c.
 struct ModArgs {
@@ -173,9 +184,16 @@ struct ModArgs {
   int32_t n_hubs;
   int32_t n_lane;
   RowPtr row_ptr;
-  const int32_t *col;
+  const int32_t *col;  // ranked: degree-order positions of the neighbours
   const float *w;
-  const int32_t *lab;
+  const int32_t *lab;  // ranked: indexed by degree-order position, else by id
+  int32_t ranked;
+  // hubs split into segments of seg_len entries (seg_hub[q] = hub of segment
+  // q, hub_pbase[h] = first segment of hub h), or n_seg = 0: whole hubs
+  int32_t n_seg;
+  int32_t seg_len;
+  const int32_t *seg_hub;
+  const int32_t *hub_pbase;
   double *tot;
   double *acc;
 };

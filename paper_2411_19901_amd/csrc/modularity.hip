@@ -84,14 +84,15 @@ __device__ __forceinline__ void mod_step(const ModArgs &m, Stage<T, long long> &
   wave_lds_sync();
 }
 
-// One lane per row: entries [beg, beg + len) of vertex v (v < 0: none).
+// One lane per row: entries [beg, beg + len) of vertex v at degree-order
+// position p (v < 0: none).
 template <int T>
-__device__ void mod_lane_rows(const ModArgs &m, Stage<T, long long> &st, int lane, int v,
+__device__ void mod_lane_rows(const ModArgs &m, Stage<T, long long> &st, int lane, int p, int v,
                               double &k_acc, double &in_acc) {
   long long beg = 0;
   int len = 0, ci = -1;
   if (v >= 0) {
-    ci = m.lab[v];
+    ci = m.lab[m.ranked ? p : v];
     beg = m.row_ptr[v];
     len = (int)(m.row_ptr[v + 1] - beg);
   }
@@ -120,16 +121,16 @@ __device__ void mod_lane_rows(const ModArgs &m, Stage<T, long long> &st, int lan
   add_by_label(m.tot, ci, ki, v >= 0 && len > 0);
 }
 
-// One wavefront per row; (pc, ps) is this wavefront's pending contribution
-// to Sigma_pc, flushed when the label changes.
-__device__ void mod_hub(const ModArgs &m, int v, double &k_acc, double &in_acc, int &pc,
-                        double &ps) {
+// One wavefront per hub segment: entries [rb, re) of the row of vertex v
+// at degree-order position p; (pc, ps) is this wavefront's pending
+// contribution to Sigma_pc, flushed when the label changes.
+__device__ void mod_hub(const ModArgs &m, int p, int v, long long rb, long long re,
+                        double &k_acc, double &in_acc, int &pc, double &ps) {
   const int lane = threadIdx.x & (kWave - 1);
   const gptr<const int32_t> col = as_global(m.col);
   const gptr<const float> wp = as_global(m.w);
   const gptr<const int32_t> lab = as_global(m.lab);
-  const int ci = lab[v];
-  const long long rb = m.row_ptr[v], re = m.row_ptr[v + 1];
+  const int ci = lab[m.ranked ? p : v];
   constexpr int U = 4;
   double ki = 0.0, in = 0.0;
   for (long long e0 = rb; e0 < re; e0 += U * kWave) {
@@ -171,16 +172,28 @@ __global__ __launch_bounds__(kBlock) void k_modularity(ModArgs m) {
   const int wib = rfl(threadIdx.x / kWave);
   const int wave = rfl(blockIdx.x * (kBlock / kWave) + wib);
   const int nwaves = gridDim.x * (kBlock / kWave);
-  const int items = m.n_hubs + (m.n_lane + kWave - 1) / kWave;
+  // hub items: one per segment, or one per whole hub without segments
+  const int hub_items = m.n_seg > 0 ? m.n_seg : m.n_hubs;
+  const int items = hub_items + (m.n_lane + kWave - 1) / kWave;
   double k_acc = 0.0, in_acc = 0.0, ps = 0.0;
   int pc = -1;
   for (int item = wave; item < items; item += nwaves) {
-    if (item < m.n_hubs) {
-      mod_hub(m, m.order[item], k_acc, in_acc, pc, ps);
+    if (item < hub_items) {
+      int h = item;
+      long long q = 0;
+      if (m.n_seg > 0) {
+        h = m.seg_hub[item];
+        q = item - m.hub_pbase[h];
+      }
+      const int v = m.order[h];
+      const long long rb = m.row_ptr[v], re = m.row_ptr[v + 1];
+      const long long b = m.n_seg > 0 ? rb + q * m.seg_len : rb;
+      const long long e = m.n_seg > 0 ? min(b + (long long)m.seg_len, re) : re;
+      mod_hub(m, h, v, b, e, k_acc, in_acc, pc, ps);
     } else {
-      const int u = (item - m.n_hubs) * kWave + lane;
+      const int u = (item - hub_items) * kWave + lane;
       const int v = u < m.n_lane ? m.order[m.n_hubs + u] : -1;
-      mod_lane_rows<kStageT>(m, stage[wib], lane, v, k_acc, in_acc);
+      mod_lane_rows<kStageT>(m, stage[wib], lane, m.n_hubs + u, v, k_acc, in_acc);
     }
   }
   if (pc >= 0 && lane == 0) atomicAdd(&m.tot[pc], ps);

@@ -53,6 +53,12 @@ __device__ __forceinline__ Pos row_at(const RowPtr &rp, int v) {
     return as_global(rp.p32)[v];
 }
 
+// Index of the labels and flags of the vertex at degree-order position p
+// (id v): its id, or its position when the graph keeps its state ranked.
+// The same index is what `col` holds for the vertex, so a row entry equal to
+// it is the vertex itself.
+__device__ __forceinline__ int state_at(const MoveArgs &a, int p, int v) { return a.ranked ? p : v; }
+
 // ---------------------------------------------------------------------------
 // Register sketch: one lane owns all K slots.
 // ---------------------------------------------------------------------------
@@ -404,8 +410,9 @@ struct HubChunks {
   int lab[D];
   float x[D];  // 0 for padding and self-loops
 
+  // self: the vertex's own index as its row entries name it
   template <class Pos>
-  __device__ __forceinline__ void load(const MoveArgs &a, int v, Pos sb, Pos end, int lane) {
+  __device__ __forceinline__ void load(const MoveArgs &a, int self, Pos sb, Pos end, int lane) {
     int c[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -414,7 +421,7 @@ struct HubChunks {
       x[d] = 0.0f;
       if (e < end) {
         c[d] = __builtin_nontemporal_load(a.col + e);
-        x[d] = (c[d] == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
+        x[d] = (c[d] == self) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
       }
     }
 #pragma unroll
@@ -425,16 +432,16 @@ struct HubChunks {
 // Call consume(lab, x, cnt) for every 64-entry chunk of [beg, end) in order
 // (cnt = entries of the chunk; lanes >= cnt hold padding).
 template <class Pos, class Consume>
-__device__ __forceinline__ void hub_feed(const MoveArgs &a, int v, Pos beg, Pos end, int lane,
+__device__ __forceinline__ void hub_feed(const MoveArgs &a, int self, Pos beg, Pos end, int lane,
                                          Consume &&consume) {
   // The chain of one hub bounds the whole iteration while the other
   // wavefronts of its SIMD stream short rows: let it issue first.
   __builtin_amdgcn_s_setprio(3);
   HubChunks<kHubDepth> cur, nxt;
-  cur.load(a, v, beg, end, lane);
+  cur.load(a, self, beg, end, lane);
   for (Pos sb = beg; sb < end; sb += kHubDepth * kWave) {
     const Pos nb = sb + kHubDepth * kWave;
-    if (nb < end) nxt.load(a, v, nb, end, lane);
+    if (nb < end) nxt.load(a, self, nb, end, lane);
 #pragma unroll 1
     for (int d = 0; d < kHubDepth; ++d) {
       const Pos base = sb + d * kWave;
@@ -458,20 +465,22 @@ __device__ __forceinline__ void hub_feed(const MoveArgs &a, int v, Pos beg, Pos 
 // scalar lane indices and no cross-lane votes; the first entry without a
 // key takes the full sketch step, after which only the lanes whose label
 // was the replaced key or is the new key change their slot.
+// p: the vertex's degree-order position.
 template <int K, bool RS, class Pos>
-__device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &scanned,
+__device__ void hub_vertex_det(const MoveArgs &a, int p, unsigned long long &scanned,
                                unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int cv = a.C[v];
-  if (a.act_cur[v] == 0) {
-    if (lane == 0) a.Cn[v] = cv;
+  const int v = a.order[p], x0 = state_at(a, p, v);
+  const int cv = a.C[x0];
+  if (a.act_cur[x0] == 0) {
+    if (lane == 0) a.Cn[x0] = cv;
     return;
   }
-  if (lane == 0) a.act_cur[v] = 0;
+  if (lane == 0) a.act_cur[x0] = 0;
   const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
   int key = -1;
   float val = 0.0f;
-  hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
+  hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
     int slot = -1;  // the slot holding this lane's label, if any
 #pragma unroll
     for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
@@ -520,7 +529,7 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
     // slot's entries added in CSR order by the slot's lane
     key = val > 0.0f ? key : -1;
     val = 0.0f;
-    hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
+    hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
       int slot = -1;
 #pragma unroll
       for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
@@ -548,7 +557,7 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
   }
   const int c = bk;
   const bool moved = c != cv && (!a.pickless || c < cv);
-  if (lane == 0) a.Cn[v] = moved ? c : cv;
+  if (lane == 0) a.Cn[x0] = moved ? c : cv;
   if (moved) {
     changed += 1;
     mark_row(a, beg, end, lane);
@@ -567,17 +576,18 @@ __device__ void hub_vertex_det(const MoveArgs &a, int v, unsigned long long &sca
 // hub_vertex_det; one entry at a time, with LDS round trips instead of
 // register votes.
 template <int K, class Pos>
-__device__ void hub_vertex_det_sv(const MoveArgs &a, int v, unsigned long long &scanned,
+__device__ void hub_vertex_det_sv(const MoveArgs &a, int p, unsigned long long &scanned,
                                   unsigned long long &changed) {
   __shared__ int sv[kBlock / kWave][2];  // per wavefront: [0] slot index, [1] minimum (bits)
   const int lane = threadIdx.x & (kWave - 1);
   int *has = sv[threadIdx.x / kWave];
-  const int cv = a.C[v];
-  if (a.act_cur[v] == 0) {
-    if (lane == 0) a.Cn[v] = cv;
+  const int v = a.order[p], x0 = state_at(a, p, v);
+  const int cv = a.C[x0];
+  if (a.act_cur[x0] == 0) {
+    if (lane == 0) a.Cn[x0] = cv;
     return;
   }
-  if (lane == 0) a.act_cur[v] = 0;
+  if (lane == 0) a.act_cur[x0] = 0;
   const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
   int key = -1;
   float val = 0.0f;
@@ -590,7 +600,7 @@ __device__ void hub_vertex_det_sv(const MoveArgs &a, int v, unsigned long long &
     wave_lds_sync();
     return s;
   };
-  hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
+  hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
     for (int t = 0; t < cnt; ++t) {
       const int c = rl(lab, t);
       const float w = rl_f(x, t);
@@ -637,7 +647,7 @@ __device__ void hub_vertex_det_sv(const MoveArgs &a, int v, unsigned long long &
     }
   }
   const bool moved = bk != cv && (!a.pickless || bk < cv);
-  if (lane == 0) a.Cn[v] = moved ? bk : cv;
+  if (lane == 0) a.Cn[x0] = moved ? bk : cv;
   if (moved) {
     changed += 1;
     mark_row(a, beg, end, lane);
@@ -649,24 +659,25 @@ __device__ void hub_vertex_det_sv(const MoveArgs &a, int v, unsigned long long &
 // chunk in CSR order through lane reads (every lane holds the same
 // candidate).
 template <class Pos>
-__device__ void hub_vertex_det_bm(const MoveArgs &a, int v, unsigned long long &scanned,
+__device__ void hub_vertex_det_bm(const MoveArgs &a, int p, unsigned long long &scanned,
                                   unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int cv = a.C[v];
-  if (a.act_cur[v] == 0) {
-    if (lane == 0) a.Cn[v] = cv;
+  const int v = a.order[p], x0 = state_at(a, p, v);
+  const int cv = a.C[x0];
+  if (a.act_cur[x0] == 0) {
+    if (lane == 0) a.Cn[x0] = cv;
     return;
   }
-  if (lane == 0) a.act_cur[v] = 0;
+  if (lane == 0) a.act_cur[x0] = 0;
   const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
   BmSketch S;
   S.clear();
-  hub_feed(a, v, beg, end, lane, [&](int lab, float x, int cnt) {
+  hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
     for (int t = 0; t < cnt; ++t) S.add(rl(lab, t), rl_f(x, t));
   });
   const int c = S.max_key(cv);
   const bool moved = c != cv && (!a.pickless || c < cv);
-  if (lane == 0) a.Cn[v] = moved ? c : cv;
+  if (lane == 0) a.Cn[x0] = moved ? c : cv;
   if (moved) {
     changed += 1;
     mark_row(a, beg, end, lane);
@@ -684,12 +695,13 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
                                            unsigned long long &scanned,
                                            unsigned long long &changed) {
   const int lane = threadIdx.x & (kWave - 1);
-  int v = -1, len = 0, cv = 0, pslot = -1;
+  int v = -1, sx = -1, len = 0, cv = 0, pslot = -1;  // sx: state index of v
   Pos beg = 0;
   bool whole = false, active = false;
   if (ASYNC && u < a.n_seg) {
     const int h = a.seg_hub[u];
     v = a.order[h];
+    sx = state_at(a, h, v);
     active = a.hub_act[h] != 0;
     const int q = u - a.hub_pbase[h];
     const Pos rb = row_at<Pos>(a.row_ptr, v), re = row_at<Pos>(a.row_ptr, v + 1);
@@ -697,12 +709,14 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
     len = (int)min((Pos)a.seg_len, (Pos)(re - beg));
     pslot = u;
   } else if (u < a.n_seg + a.n_lane) {
-    v = a.order[a.n_hubs + (u - a.n_seg)];
+    const int p = a.n_hubs + (u - a.n_seg);
+    v = a.order[p];
+    sx = state_at(a, p, v);
     whole = true;
-    active = a.act_cur[v] != 0;
-    cv = a.C[v];
+    active = a.act_cur[sx] != 0;
+    cv = a.C[sx];
     if (active) {
-      a.act_cur[v] = 0;
+      a.act_cur[sx] = 0;
       beg = row_at<Pos>(a.row_ptr, v);
       len = (int)(row_at<Pos>(a.row_ptr, v + 1) - beg);
     }
@@ -710,7 +724,7 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
   if (!active) len = 0;
   typename SketchOf<K>::type S;
   S.clear();
-  const int kept = staged_scan<typename SketchOf<K>::type, kStageT, KEEP>(a, st, lane, beg, len, v, S);
+  const int kept = staged_scan<typename SketchOf<K>::type, kStageT, KEEP>(a, st, lane, beg, len, sx, S);
   scanned += (unsigned long long)len;
   int c = cv;
   if constexpr (RS) {
@@ -718,7 +732,7 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
     // their sketches are merged (k_hub_rescan)
     Rescan<K> R;
     R.from(S);
-    staged_rows<kStageT>(a, st, lane, beg, whole ? len : 0, v,
+    staged_rows<kStageT>(a, st, lane, beg, whole ? len : 0, sx,
                          [&](int lab, float x) { R.add(lab, x); });
     if (whole) c = R.best(cv);
   } else {
@@ -737,9 +751,9 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
   } else if (whole) {
     moved = active && c != cv && (!a.pickless || c < cv);
     if (ASYNC) {
-      if (moved) a.C[v] = c;
+      if (moved) a.C[sx] = c;
     } else {
-      a.Cn[v] = moved ? c : cv;
+      a.Cn[sx] = moved ? c : cv;
     }
   }
   // every lane reaches here: the marking pass is wavefront-cooperative
@@ -774,6 +788,7 @@ __device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
   a.act_cur = as_global(d.act[iter & 1]);
   a.act_next = as_global(d.act[(iter + 1) & 1]);
   a.order = as_global(d.order);
+  a.ranked = d.ranked;
   a.n_hubs = d.n_hubs;
   a.n_lane = d.n_lane;
   a.seg_len = d.seg_len;
@@ -839,11 +854,11 @@ __device__ __forceinline__ void move_body(const Launch &L) {
     const int hub_items = ASYNC ? 0 : a.n_hubs;
     if (local < hub_items) {
       if constexpr (K == 0)
-        hub_vertex_det_bm<Pos>(a, a.order[local], scanned_w, changed_w);
+        hub_vertex_det_bm<Pos>(a, local, scanned_w, changed_w);
       else if constexpr (SV)
-        hub_vertex_det_sv<K, Pos>(a, a.order[local], scanned_w, changed_w);
+        hub_vertex_det_sv<K, Pos>(a, local, scanned_w, changed_w);
       else
-        hub_vertex_det<K, RS, Pos>(a, a.order[local], scanned_w, changed_w);
+        hub_vertex_det<K, RS, Pos>(a, local, scanned_w, changed_w);
     } else
       lane_units<K, ASYNC, RS, Pos, kKeepCols<K, RS, Pos, SV>>(
           a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane, changed_w);
@@ -893,9 +908,9 @@ __global__ void k_hub_snapshot(Launch L) {
     const GraphDesc &d = L.d[g];
     if (d.st->done) continue;
     const int h = t - L.prefix_hubs[g];
-    const int v = d.order[h];
-    d.hub_act[h] = d.act[0][v];
-    d.act[0][v] = 0;
+    const int x = d.ranked ? h : d.order[h];
+    d.hub_act[h] = d.act[0][x];
+    d.act[0][x] = 0;
   }
 }
 
@@ -1093,14 +1108,14 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
     const MoveArgs a = make_args(gd, iter);
     const int it = item - L.prefix_merge[g], ni = rfl(merge_items(L, g));
     const int h = merge_hub(it, lane / kHubLanes, ni);
-    int v = -1, p0 = 0, np = 0, cv = 0;
+    int x = -1, p0 = 0, np = 0, cv = 0;  // x: the hub's state index
     bool active = false;
     if (h < a.n_hubs) {
-      v = a.order[h];
+      x = state_at(a, h, a.order[h]);
       active = a.hub_act[h] != 0;
       p0 = a.hub_pbase[h];
       np = a.hub_pbase[h + 1] - p0;
-      cv = a.C[v];
+      cv = a.C[x];
     }
     int c = cv;
     const bool small = active && np <= kWave;
@@ -1205,7 +1220,7 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
     }
     if constexpr (!RS) {
       const bool moved = active && c != cv && (!a.pickless || c < cv);
-      if (moved && sub == 0) a.C[v] = c;
+      if (moved && sub == 0) a.C[x] = c;
       changed_w += (unsigned long long)__popcll(__ballot(moved && sub == 0));
       if (sub == 0) record_moved_hub(a, h, moved);
     }
@@ -1240,7 +1255,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
     const int u = item - L.prefix_segs[g];
     const int h = a.seg_hub[u];
     if (a.hub_act[h] == 0) continue;
-    const int v = a.order[h];
+    const int v = a.order[h], self = state_at(a, h, v);
     const int q = u - a.hub_pbase[h];
     const long long rb = a.row_ptr[v], re = a.row_ptr[v + 1];
     const long long beg = rb + (long long)q * a.seg_len, end = min(beg + a.seg_len, re);
@@ -1262,7 +1277,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
         x[t] = 0.0f;
         if (e < end) {
           const int j = __builtin_nontemporal_load(a.col + e);
-          x[t] = (j == v) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
+          x[t] = (j == self) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
           lab[t] = a.C[j];
         }
       }
@@ -1306,14 +1321,14 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
     const MoveArgs a = make_args(gd, iter);
     const int it = item - L.prefix_merge[g], ni = rfl(merge_items(L, g));
     const int h = merge_hub(it, lane / kHubLanes, ni);
-    int v = -1, p0 = 0, np = 0, cv = 0;
+    int x = -1, p0 = 0, np = 0, cv = 0;  // x: the hub's state index
     bool active = false;
     if (h < a.n_hubs) {
-      v = a.order[h];
+      x = state_at(a, h, a.order[h]);
       active = a.hub_act[h] != 0;
       p0 = a.hub_pbase[h];
       np = a.hub_pbase[h + 1] - p0;
-      cv = a.C[v];
+      cv = a.C[x];
     }
     float tot[K];
 #pragma unroll
@@ -1357,7 +1372,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
       }
     }
     const bool moved = active && c != cv && (!a.pickless || c < cv);
-    if (moved && sub == 0) a.C[v] = c;
+    if (moved && sub == 0) a.C[x] = c;
     changed_w += (unsigned long long)__popcll(__ballot(moved && sub == 0));
     if (sub == 0) record_moved_hub(a, h, moved);
   }
@@ -1441,7 +1456,7 @@ __global__ __launch_bounds__(256) void k_hub_shared(Launch L) {
     const MoveArgs a = make_args(gd, gd.st->iter);
     const int h = item - L.prefix_hubs[g];
     if (a.hub_act[h] == 0) continue;
-    const int v = a.order[h];
+    const int v = a.order[h], self = state_at(a, h, v);
     if (threadIdx.x < K) {
       key[threadIdx.x] = -1;
       val[threadIdx.x] = 0.0f;
@@ -1450,13 +1465,13 @@ __global__ __launch_bounds__(256) void k_hub_shared(Launch L) {
     const long long rb = a.row_ptr[v], re = a.row_ptr[v + 1];
     for (long long e = rb + threadIdx.x; e < re; e += blockDim.x) {
       const int j = __builtin_nontemporal_load(a.col + e);
-      if (j == v) continue;
+      if (j == self) continue;
       const float w = a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f;
       shared_add<K>(key, val, a.C[j], w);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      const int cv = a.C[v];
+      const int cv = a.C[self];
       int c = cv;
       float bv = 0.0f;
       for (int s = 0; s < K; ++s)
@@ -1466,7 +1481,7 @@ __global__ __launch_bounds__(256) void k_hub_shared(Launch L) {
         }
       const bool moved = c != cv && (!a.pickless || c < cv);
       if (moved) {
-        a.C[v] = c;
+        a.C[self] = c;
         atomicAdd(gd.dN + gd.st->iter, 1ull);
       }
       a.hub_act[h] = moved ? 1 : 0;  // k_hub_mark flags the neighbours
@@ -1483,19 +1498,22 @@ __global__ void k_finish(Launch L) {
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < L.G; g += gridDim.x * blockDim.x) {
     const GraphDesc &d = L.d[g];
     GraphStatus *st = d.st;
+    int changed = 0;  // dN of the iteration this launch ran (0: none ran)
     if (!st->done) {
       const int l = st->iter;
       const bool pl = d.rho > 0 && l % d.rho == 0;
       const double frac = (double)d.dN[l] / (double)d.n;
       const bool stop = (!pl && frac < d.tol) || l + 1 >= d.max_iter;
+      changed = (int)d.dN[l];  // at most n < 2^31
       st->iter = l + 1;
       if (stop) {
         st->done = 1;
         atomicAdd(L.finished, 1);
       }
     }
-    L.status_out[2 * g] = st->iter;
-    L.status_out[2 * g + 1] = st->done;
+    L.status_out[3 * g] = st->iter;
+    L.status_out[3 * g + 1] = st->done;
+    L.status_out[3 * g + 2] = changed;
   }
 }
 

@@ -38,6 +38,7 @@ LPA_HUB_SHARED = 0x800
 LPA_CAPTURE = 0x1000
 LPA_SHARED_VARS = 0x2000
 LPA_STREAM_CSR = 0x4000
+LPA_RANKED_LAYOUT = 0x8000
 
 MODES = {"det": LPA_MODE_DET, "async": LPA_MODE_ASYNC}
 # per-vertex rule: the k-slot weighted Misra-Gries sketch, or the
@@ -87,6 +88,7 @@ def load(path: str = LIB_PATH):
                                     ctypes.c_double, ctypes.c_int, ctypes.c_uint64,
                                     ctypes.POINTER(LpaConfig), pH]),
         "lpa_reset": (ctypes.c_int, [H]),
+        "lpa_set_stream": (ctypes.c_int, [H, ctypes.c_void_p]),
         "lpa_step": (ctypes.c_int, [H, i64p, ip]),
         "lpa_run": (ctypes.c_int, [H, ip]),
         "lpa_modularity": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
@@ -319,7 +321,7 @@ class LPA:
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
                  stream=None, workspace=None, rule: str = "mg", rescan: bool = False,
                  hub_shared: bool = False, capture: bool = False, shared_vars: bool = False,
-                 stream_csr: bool = False, stream_chunk_kib: int = 0):
+                 stream_csr: bool = False, stream_chunk_kib: int = 0, ranked: bool = False):
         import torch
 
         def usable(t):  # device memory, or pinned host memory the device maps
@@ -342,7 +344,8 @@ class LPA:
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_VALIDATE if validate else 0)
                      | (LPA_RESCAN if rescan else 0) | (LPA_HUB_SHARED if hub_shared else 0)
                      | (LPA_SHARED_VARS if shared_vars else 0)
-                     | (LPA_CAPTURE if capture else 0) | (LPA_STREAM_CSR if stream_csr else 0))
+                     | (LPA_CAPTURE if capture else 0) | (LPA_STREAM_CSR if stream_csr else 0)
+                     | (LPA_RANKED_LAYOUT if ranked else 0))
         cfg.stream_chunk_kib = stream_chunk_kib
         cfg.rho = rho
         if stream is None:
@@ -366,6 +369,11 @@ class LPA:
 
     def step(self) -> Tuple[int, bool]:
         return lpa_step(self.h)
+
+    def set_stream(self, stream) -> None:
+        """Enqueue all later work of this handle on ``stream`` (a torch stream)."""
+        _check(load().lpa_set_stream(self.h, stream.cuda_stream), "lpa_set_stream", self.h)
+        self.stream = stream
 
     def run(self) -> int:
         return lpa_run(self.h)
@@ -431,10 +439,12 @@ class LPA:
 
 
 def workspace_bytes(n: int, nnz: int, k: int = 8, max_iter: int = 20, mode: str = "det",
-                    lane_max_degree: int = 0, rule: str = "mg", rescan: bool = False) -> int:
+                    lane_max_degree: int = 0, rule: str = "mg", rescan: bool = False,
+                    ranked: bool = False) -> int:
     """Device bytes one handle needs (for LPA(..., workspace=...))."""
     cfg = lpa_config_default()
-    cfg.flags = MODES[mode] | RULES[rule] | LPA_VALIDATE | (LPA_RESCAN if rescan else 0)
+    cfg.flags = (MODES[mode] | RULES[rule] | LPA_VALIDATE | (LPA_RESCAN if rescan else 0)
+                 | (LPA_RANKED_LAYOUT if ranked else 0))
     cfg.lane_max_degree = lane_max_degree
     return lpa_workspace_bytes(n, nnz, k, max_iter, cfg)
 

@@ -108,7 +108,7 @@ def test_bm_paper_rule_flag():
     cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RULE_BM_PAPER
     assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_OK
-    cfg.flags = lpa.LPA_MODE_DET | 0x8000
+    cfg.flags = lpa.LPA_MODE_DET | 0x10000
     assert L.lpa_workspace_bytes(10, 20, 1, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_UNSUPPORTED
     # shared variables instead of votes: det sketch rule without double scan only
@@ -189,3 +189,18 @@ def test_stream_csr_config():
     cfg.reserved[0] = 1
     assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_ARG
+
+
+def test_ranked_layout_workspace():
+    # the ranked layout adds the rewritten column indices (4 B per entry) and
+    # a 4 B per vertex transfer buffer; it cannot be combined with streaming
+    for mode in ("det", "async"):
+        plain = lpa.workspace_bytes(5000, 80000, k=8, mode=mode)
+        ranked = lpa.workspace_bytes(5000, 80000, k=8, mode=mode, ranked=True)
+        assert ranked >= plain + 4 * 80000 + 4 * 5000
+        assert ranked <= plain + 4 * 80000 + 4 * 5000 + 1024
+    L = lpa.load()
+    out = ctypes.c_size_t(0)
+    cfg = lpa.lpa_config_default()
+    cfg.flags = lpa.LPA_MODE_DET | lpa.LPA_RANKED_LAYOUT | lpa.LPA_STREAM_CSR
+    assert L.lpa_workspace_bytes(10, 20, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == lpa.LPA_ERR_ARG

@@ -44,6 +44,37 @@ def test_bench_json_line(monkeypatch, capsys):
     assert r["achieved"] > 0 and abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-3
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["sample"]
+    q = d["quality"]
+    assert -0.5 <= q["q_async"] <= 1 and -0.5 <= q["q_det"] <= 1
+    assert q["q_exact_oracle"] == c["exact_rule_run"]["q"]
+    assert 1 <= q["det_iterations"] <= 20
+
+
+def _json_line(out):
+    lines = [ln for ln in out.splitlines() if ln.startswith("{")]
+    assert len(lines) == 1, out
+    return json.loads(lines[0])
+
+
+@pytest.mark.gpu
+def test_bench_batch_and_serve_lines(monkeypatch, capsys):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "batch", "--batch-graphs", "16",
+                                      "--steps", "1", "--warmup", "1", "--capture"])
+    bench.main()
+    d = _json_line(capsys.readouterr().out)
+    assert d["unit"] == "graphs/s" and d["value"] > 0 and d["identical_labels_and_iterations"]
+    assert d["config"]["captured"] is True
+    assert d["cpu_baseline"]["labels_equal_gpu_batched"] is True
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "serve", "--requests", "12",
+                                      "--serve-max-scale", "14", "--serve-loads", "1.0",
+                                      "--warmup", "1"])
+    bench.main()
+    d = _json_line(capsys.readouterr().out)
+    assert d["unit"] == "graphs/s" and d["value"] > 0 and d["identical_to_alone"]
+    assert d["config"]["overlapped_admission"] is True
+    assert d["p99_ms"] >= d["p50_ms"] > 0
 
 
 def test_bench_refuses_several_gpus(monkeypatch, capsys):

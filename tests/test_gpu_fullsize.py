@@ -11,6 +11,8 @@
 * Modularity of the asynchronous run on R-MAT scale 24 (the benchmark
   configuration) against the oracle's fp64 modularity of the same labels.
 * The 4096 x 4096 rewired grid, det mode, whole run.
+* The ranked state layout: R-MAT scale 22 det whole run against the oracle,
+  R-MAT scale 24 async modularity.
 """
 import numpy as np
 import pytest
@@ -86,6 +88,25 @@ def whole_run_exact(g, k, **kw):
 def test_rmat22_det_whole_run_k_sweep(k):
     it = whole_run_exact(graph(22, False), k)
     print(f"rmat22 det k={k}: {it} iterations equal to the oracle")
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_ranked_det_whole_run():
+    # the ranked state layout at full size: same run as the default layout
+    it = whole_run_exact(graph(22, False), 8, ranked=True)
+    print(f"rmat22 det k=8 ranked: {it} iterations equal to the oracle")
+
+
+@pytest.mark.timeout(600)
+def test_rmat24_ranked_async_modularity_parity():
+    g = graph(24, True)
+    s = solver(g, k=8, mode="async", ranked=True)
+    it = s.run()
+    assert 1 <= it <= 20
+    lab = s.labels(device=False)
+    assert lab.min() >= 0 and lab.max() < g.n
+    assert abs(s.modularity() - oracle.modularity(g.row_ptr, g.col, g.w, lab)) <= 1e-9
+    s.close()
 
 
 @pytest.mark.timeout(900)

@@ -86,9 +86,10 @@ def test_every_vertex_is_a_hub():
     assert segs.min() > 64 and segs.max() >= 300
 
 
-def run_and_check(g, k, rescan, iters=4):
+def run_and_check(g, k, rescan, iters=4, ranked=False):
     rp, col, w = to_dev(g)
-    s = lpa.LPA(rp, col, w, k=k, mode="async", lane_max_degree=S, rho=RHO, rescan=rescan)
+    s = lpa.LPA(rp, col, w, k=k, mode="async", lane_max_degree=S, rho=RHO, rescan=rescan,
+                ranked=ranked)
     try:
         for _ in range(iters):
             C, act, l = s.get_state()

@@ -193,6 +193,30 @@ def test_checkpoint_resume_bit_exact():
     b.close()
 
 
+def test_profile_marks_untimed_iterations():
+    # iterations whose move kernel was not timed read -1, and reading them
+    # leaves the handle usable (no HIP error from events never recorded)
+    g = graph("rmat12")
+    rp, col, w = to_dev(g)
+    s = lpa.LPA(rp, col, w, k=8, max_iter=20)
+    s.step()  # before profiling
+    s.profile(True)
+    s.step()
+    s.step()
+    ms = s.move_ms()
+    assert len(ms) == 3 and ms[0] == -1.0 and ms[1] >= 0.0 and ms[2] >= 0.0
+    lab, flags, it = s.get_state()
+    s.set_state(lab, flags, it)  # restored at iteration 3: nothing timed yet
+    assert (s.move_ms() == -1.0).all()
+    s.run()
+    ms = s.move_ms()
+    assert (ms[:3] == -1.0).all() and (ms[3:] >= 0.0).all()
+    s.reset()
+    s.run()
+    assert (s.move_ms() >= 0.0).all()
+    s.close()
+
+
 def test_reset_reproduces():
     g = graph("rmat12")
     rp, col, w = to_dev(g)

@@ -130,3 +130,46 @@ def test_poisson_arrivals_rate():
     a = poisson_arrivals(20000, rate=50.0, seed=3)
     assert np.all(np.diff(a) > 0)
     assert abs(len(a) / a[-1] - 50.0) < 2.0
+
+
+class SlowAdmitBackend(OracleBackend):
+    """Admission that takes a while (as copies and binning do), called from
+    the server's admission thread."""
+
+    def admit(self, req, overlap=False):
+        assert overlap
+        import time
+        time.sleep(0.002)
+        return _State(req, self.k)
+
+
+def test_overlapped_admission_equals_solo():
+    gs = request_mix(count=10, seed=31)
+    be = SlowAdmitBackend()
+    srv = Server(be, max_resident=4, hbm_reserve=0, overlap_admission=True)
+    t0 = srv.clock()
+    arrivals = poisson_arrivals(len(gs), rate=3000.0, seed=7, start=t0)
+    for g, a in zip(gs, arrivals):
+        srv.submit(g.row_ptr, g.col, g.w, arrival=float(a))
+    srv.run_until_idle()
+    srv.close()
+    assert be.max_seen <= 4
+    check_results(srv, gs)
+    for r in srv.completed:
+        assert r.admitted >= r.arrival and r.finished >= r.admitted
+
+
+def test_overlapped_admission_waits_for_memory():
+    gs = request_mix(count=8, seed=8)
+    be = SlowAdmitBackend()
+    budget = max(be.bytes_needed(type("R", (), {"n": g.n, "nnz": g.nnz})) for g in gs) + 10
+    srv = Server(be, max_resident=64, hbm_reserve=0, overlap_admission=True)
+    # free memory = budget minus what admitted requests hold
+    srv.free_bytes = lambda: budget - sum(r.bytes_needed for r in srv.resident + list(srv.ready))
+    for g in gs:
+        srv.submit(g.row_ptr, g.col, g.w, arrival=0.0)
+    srv.run_until_idle()
+    srv.close()
+    assert srv.waits_for_memory > 0
+    assert be.max_bytes <= budget
+    check_results(srv, gs)
