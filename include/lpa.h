@@ -327,6 +327,20 @@ int lpa_progress(const lpa_handle *h, int *iteration, int *finished);
  * is out of range.  Synchronises. */
 int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q);
 
+/* lpa_modularity for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc):
+ * the same result (|dQ| <= 1e-9 against lpa_modularity: fp64 sums in another
+ * order), but the per-community totals live in a static device array of
+ * the library instead of a per-handle allocation, so the call allocates
+ * nothing, ever.  Limit: n <= 2^21 vertices (LPA_ERR_UNSUPPORTED above; the
+ * array holds 2^21 + 32 doubles, 16 MiB per device the library runs on, kept
+ * until the process ends).  The handle's device must be current
+ * (LPA_ERR_ARG otherwise).  Every call on one device shares that array:
+ * calls that overlap on one GPU (other streams or threads) race and give
+ * wrong results; serialise them.  Other arguments, checks and errors as in
+ * lpa_modularity.  Synchronises. */
+int lpa_modularity_noalloc(lpa_handle *h, const int32_t *labels, double *q);
+
 /* Copy the current labels (int32[n]) to out, a host pointer if out_is_host
  * is nonzero, else a device pointer.  Synchronises. */
 int lpa_get_labels(lpa_handle *h, int32_t *out, int out_is_host);

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <array>
 #include <string>
@@ -1815,6 +1816,39 @@ int modularity_into(lpa_handle *h, const int32_t *labels, double *q, double *tot
   return LPA_OK;
 }
 
+// The allocation-free variant's scratch: the community totals of up to
+// kScratchVertices vertices and the four accumulators, one copy per device
+// (held until the process ends).  Host code never uses the symbol itself:
+// its device address is looked up once per device (scratch_on_device) and
+// that address is what the kernels receive.
+constexpr int kScratchVertices = 1 << 21;
+constexpr int kScratchDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchVertices + 32];
+
+namespace {
+
+std::mutex scratch_mu;
+double *scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call made with that device current; nullptr on failure.
+double *scratch_on_device(int dev) {
+  if (dev < 0 || dev >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    scratch_ptr[dev] = (double *)p;
+  }
+  return scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1841,6 +1875,31 @@ int lpa_modularity(lpa_handle *h, const int32_t *labels, double *q) {
     hipLaunchKernelGGL(k_zero_d, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, h->mod_tot, n);
   }
   return modularity_into(h, labels, q, h->mod_tot, h->mod_acc);
+}
+
+int lpa_modularity_noalloc(lpa_handle *h, const int32_t *labels, double *q) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!q) return LPA_ERR_ARG;
+  const int n = h->n;
+  if (n > kScratchVertices)
+    return set_err(h, LPA_ERR_UNSUPPORTED,
+                   "lpa_modularity_noalloc: more vertices than its static scratch holds (2^21)");
+  if (n == 0) {
+    *q = 0.0;
+    return LPA_OK;
+  }
+  int dev = -1;
+  HIP_TRY(h, hipGetDevice(&dev));
+  if (dev != h->device)
+    return set_err(h, LPA_ERR_ARG, "lpa_modularity_noalloc: the handle's device must be current");
+  double *sp = scratch_on_device(dev);
+  if (!sp) return set_err(h, LPA_ERR_HIP, "lpa_modularity_noalloc: scratch address lookup failed");
+  double *tot = sp, *acc = sp + kScratchVertices;
+  // the totals must start at zero whatever an earlier call left behind
+  hipLaunchKernelGGL(k_zero_d, dim3(grid_for(n)), dim3(kAuxBlock), 0, h->stream, tot, n);
+  LAUNCH_TRY(h, "scratch clear");
+  return modularity_into(h, labels, q, tot, acc);
 }
 
 int lpa_get_state(lpa_handle *h, int32_t *labels, uint8_t *unprocessed, int *iteration,

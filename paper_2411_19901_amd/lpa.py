@@ -92,6 +92,8 @@ def load(path: str = LIB_PATH):
         "lpa_step": (ctypes.c_int, [H, i64p, ip]),
         "lpa_run": (ctypes.c_int, [H, ip]),
         "lpa_modularity": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+        "lpa_modularity_noalloc": (ctypes.c_int, [H, ctypes.c_void_p,
+                                                  ctypes.POINTER(ctypes.c_double)]),
         "lpa_get_labels": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_int]),
         "lpa_get_trace": (ctypes.c_int, [H, i64p, i64p, ctypes.c_int, ip]),
         "lpa_get_state": (ctypes.c_int, [H, ctypes.c_void_p, ctypes.c_void_p, ip, ctypes.c_int]),
@@ -198,6 +200,13 @@ def lpa_reset(h) -> None:
 def lpa_modularity(h, labels_ptr: Optional[int] = None) -> float:
     q = ctypes.c_double(0.0)
     _check(load().lpa_modularity(h, labels_ptr or None, ctypes.byref(q)), "lpa_modularity", h)
+    return float(q.value)
+
+
+def lpa_modularity_noalloc(h, labels_ptr: Optional[int] = None) -> float:
+    q = ctypes.c_double(0.0)
+    _check(load().lpa_modularity_noalloc(h, labels_ptr or None, ctypes.byref(q)),
+           "lpa_modularity_noalloc", h)
     return float(q.value)
 
 

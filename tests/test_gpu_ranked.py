@@ -126,6 +126,7 @@ def test_ranked_device_labels_and_given_modularity():
     assert abs(q - oracle.modularity(g.row_ptr, g.col, g.w, given)) <= 1e-9
     q0 = s.modularity()
     assert abs(q0 - oracle.modularity(g.row_ptr, g.col, g.w, host_lab)) <= 1e-9
+    assert abs(lpa.lpa_modularity_noalloc(s.h) - q0) <= 1e-9
     core, _ = s.memory()
     s.close()
     plain = lpa.LPA(rp, col, w, k=8)
