@@ -212,19 +212,30 @@ def bench_batch(args, cpu_sample: int = 0):
     log(f"[bench] batch of {len(gs)} graphs: {nv} vertices, {ne} entries, generated in {gen_s:.1f}s")
     stream = torch.cuda.current_stream(dev)
     t = time.perf_counter()
-    solvers = [lpa.LPA(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), None,
-                       k=args.k, tol=args.tol, max_iter=args.max_iter, mode=args.mode,
-                       stream=stream) for g in gs]
+    tensors = [(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), None)
+               for g in gs]
+    solvers = [lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
+                       mode=args.mode, stream=stream) for rp, col, w in tensors]
     torch.cuda.synchronize()
     init_s = time.perf_counter() - t
     batch = lpa.Batch(len(solvers), k=args.k, mode=args.mode, stream=stream,
                       capture=args.capture)
-
-    def digest():
-        h = hashlib.sha256()
-        for s in solvers:
-            h.update(s.labels(device=False).tobytes())
-        return h.hexdigest()[:16]
+    tuned = None
+    if args.autotune:
+        # per-graph lane thresholds (one tuning per shape group) and the
+        # launch's workgroup cap, chosen untimed; a second set of handles
+        from paper_2411_19901_amd import tune
+        t = time.perf_counter()
+        tuned = tune.tune_batch(tensors, k=args.k, mode=args.mode)
+        tune_s = time.perf_counter() - t
+        log(f"[bench] batch autotune in {tune_s:.1f}s: groups {tuned['groups']}, "
+            f"workgroups {tuned['move_blocks_per_cu']} ({tuned['batch_ms']})")
+        t_solvers = [lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
+                             mode=args.mode, stream=stream, lane_max_degree=S)
+                     for (rp, col, w), S in zip(tensors, tuned["lane_max_degree"])]
+        t_batch = lpa.Batch(len(t_solvers), k=args.k, mode=args.mode, stream=stream,
+                            capture=args.capture,
+                            move_blocks_per_cu=tuned["move_blocks_per_cu"])
 
     def solo():
         for s in solvers:
@@ -235,8 +246,15 @@ def bench_batch(args, cpu_sample: int = 0):
         batch.reset(solvers)
         batch.run(solvers)
 
+    def batched_tuned():
+        t_batch.reset(t_solvers)
+        t_batch.run(t_solvers)
+
     timings = {}
-    for name, fn in (("solo", solo), ("batched", batched)):
+    legs = [("solo", solo, solvers), ("batched", batched, solvers)]
+    if tuned is not None:
+        legs.append(("tuned", batched_tuned, t_solvers))
+    for name, fn, which in legs:
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -245,10 +263,16 @@ def bench_batch(args, cpu_sample: int = 0):
             fn()
         torch.cuda.synchronize()
         timings[name] = (time.perf_counter() - t0) / args.steps
-        timings[name + "_digest"] = digest()
-        timings[name + "_iters"] = [s.iterations() for s in solvers]
+        h = hashlib.sha256()
+        for s in which:
+            h.update(s.labels(device=False).tobytes())
+        timings[name + "_digest"] = h.hexdigest()[:16]
+        timings[name + "_iters"] = [s.iterations() for s in which]
     same = (timings["solo_digest"] == timings["batched_digest"]
             and timings["solo_iters"] == timings["batched_iters"])
+    if tuned is not None:
+        same = (same and timings["tuned_digest"] == timings["solo_digest"]
+                and timings["tuned_iters"] == timings["solo_iters"])
     scanned = sum(int(s.trace()[1].sum()) for s in solvers)
     res = {
         "metric": "batched graphs/s", "value": round(len(gs) / timings["batched"], 2),
@@ -268,6 +292,21 @@ def bench_batch(args, cpu_sample: int = 0):
         "init_s": round(init_s, 2), "gen_s": round(gen_s, 1),
         "max_iterations": max(timings["batched_iters"]),
     }
+    if tuned is not None:
+        # the headline is the tuned launch; the default shape beside it
+        res["value"] = round(len(gs) / timings["tuned"], 2)
+        res["ms_per_step"] = round(timings["tuned"] * 1e3, 3)
+        res["speedup_vs_solo"] = round(timings["solo"] / timings["tuned"], 3)
+        res["default_shape_graphs_per_s"] = round(len(gs) / timings["batched"], 2)
+        res["autotune"] = {"move_blocks_per_cu": tuned["move_blocks_per_cu"],
+                           "lane_max_degree_by_group": tuned["groups"],
+                           "batch_ms_by_blocks": {str(b): round(v, 3)
+                                                  for b, v in tuned["batch_ms"].items()},
+                           "seconds": round(tune_s, 2)}
+        res["config"]["autotuned"] = True
+        t_batch.close()
+        for s in t_solvers:
+            s.close()
     if cpu_sample > 0:
         res["cpu_baseline"] = batch_cpu_baseline(gs, solvers, args, cpu_sample)
     batch.close()
@@ -447,6 +486,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=20)
     ap.add_argument("--tol", type=float, default=0.05)
     ap.add_argument("--lane-max-degree", type=int, default=0)
+    ap.add_argument("--move-blocks-per-cu", type=int, default=0,
+                    help="cap on resident move-kernel workgroups per CU (0 = all that fit)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="graph", choices=["graph", "batch", "serve"],
@@ -552,7 +593,9 @@ def main():
         tuned["seconds"] = round(time.perf_counter() - t, 2)
         tuned["table"] = {str(k_): round(v, 4) for k_, v in tuned["table"].items()}
         args.lane_max_degree = tuned["lane_max_degree"]
-        log(f"[bench] autotuned lane_max_degree = {args.lane_max_degree} ({tuned['table']})")
+        args.move_blocks_per_cu = tuned["move_blocks_per_cu"]
+        log(f"[bench] autotuned lane_max_degree = {args.lane_max_degree}, move_blocks_per_cu = "
+            f"{args.move_blocks_per_cu} ({tuned['table']})")
     free0, _ = torch.cuda.mem_get_info(dev)
     t = time.perf_counter()
     def make_solver(ranked):
@@ -561,6 +604,7 @@ def main():
                        rescan=args.rescan, hub_shared=args.hub_shared,
                        shared_vars=args.shared_vars, stream_csr=args.stream_csr,
                        stream_chunk_kib=args.stream_chunk_kib, ranked=ranked,
+                       move_blocks_per_cu=args.move_blocks_per_cu,
                        check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
 
     solver = make_solver(args.ranked)
@@ -614,6 +658,7 @@ def main():
                                                                 else 4096),
                    "rescan": args.rescan, "offsets": 64 if args.offsets64 else 32,
                    "ranked_layout": bool(args.ranked),
+                   "move_blocks_per_cu": args.move_blocks_per_cu,
                    "mode": args.mode,
                    "tol": args.tol, "max_iter": args.max_iter, "rho": 8,
                    "step": "lpa_reset + lpa_run (all iterations to convergence)"},
@@ -650,6 +695,7 @@ def main():
     }
     if tuned is not None:
         result["autotune"] = {"lane_max_degree": tuned["lane_max_degree"],
+                              "move_blocks_per_cu": tuned["move_blocks_per_cu"],
                               "ns_per_entry": tuned["table"], "seconds": tuned["seconds"]}
     del labels
     solver.close()
@@ -706,7 +752,7 @@ def main():
     if not args.no_batch and args.graph == "rmat" and args.scale == 24:
         log("[bench] batched workload (512 planted-partition graphs, det, captured)")
         ba = copy.copy(args)
-        ba.mode, ba.capture, ba.k = "det", True, 8
+        ba.mode, ba.capture, ba.k, ba.autotune = "det", True, 8, True
         ba.steps, ba.warmup = min(args.steps, 5), 1
         result["batch"] = bench_batch(ba, 0 if args.no_cpu_baseline else 8)
         torch.cuda.empty_cache()

@@ -204,7 +204,13 @@ typedef struct lpa_config {
                               KiB of column indices (the weights double
                               it); 0 = 262144 (256 MiB).  Ignored
                               otherwise. */
-  int32_t reserved[3];     /* must be zero */
+  int32_t move_blocks_per_cu; /* launch at most this many workgroups of the
+                              move kernel per compute unit (0 = as many as
+                              are resident at once; 1..64).  Fewer
+                              resident wavefronts trade latency hiding for
+                              cache share; the autotuner picks it.  Never
+                              changes LPA_MODE_DET results. */
+  int32_t reserved[2];     /* must be zero */
 } lpa_config;
 
 typedef struct lpa_handle lpa_handle;

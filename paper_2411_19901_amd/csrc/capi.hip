@@ -389,6 +389,7 @@ struct lpa_batch {
   int check_every = 0;
   int cus = 1;
   int grid_cap[2] = {1, 1};  // resident k_move workgroups: int32 / int64 positions
+  int blocks_cap = 0;        // lpa_config.move_blocks_per_cu (0: as many as fit)
   bool wide = false;         // a loaded graph has int64 row offsets
   void *dblock = nullptr;  // device: descriptors, prefixes, finished counter, status
   GraphDesc *d_desc = nullptr;
@@ -774,10 +775,11 @@ int batch_alloc(lpa_batch *b) {
   b->device = dev;
   if (hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return LPA_ERR_HIP;
-  b->grid_cap[0] = b->cus * move_blocks_per_cu(b->k, b->async_mode, b->rescan, b->shared_vars,
-                                                false);
-  b->grid_cap[1] = b->cus * move_blocks_per_cu(b->k, b->async_mode, b->rescan, b->shared_vars,
-                                                true);
+  for (int wide = 0; wide < 2; ++wide) {
+    int per_cu = move_blocks_per_cu(b->k, b->async_mode, b->rescan, b->shared_vars, wide != 0);
+    if (b->blocks_cap > 0 && b->blocks_cap < per_cu) per_cu = b->blocks_cap;
+    b->grid_cap[wide] = b->cus * per_cu;
+  }
   if (b->capture && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     return LPA_ERR_HIP;
@@ -1007,8 +1009,9 @@ int lpa_pointer_location(const void *ptr, int *location) {
 }
 
 static int check_config(const lpa_config &cfg) {
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 2; ++i)
     if (cfg.reserved[i] != 0) return LPA_ERR_ARG;
+  if (cfg.move_blocks_per_cu < 0 || cfg.move_blocks_per_cu > 64) return LPA_ERR_ARG;
   if (cfg.rho < 0 || cfg.lane_max_degree < 0 || cfg.lane_max_degree > 65536 ||
       cfg.check_every < 0 || cfg.stream_chunk_kib < 0)
     return LPA_ERR_ARG;
@@ -1563,6 +1566,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
   h->self->async_mode = h->async_mode;
   h->self->stream = h->stream;
   h->self->check_every = h->check_every;
+  h->self->blocks_cap = cfg.move_blocks_per_cu;
   if ((rc = batch_alloc(h->self)) != LPA_OK) return bail(rc);
   if ((rc = enqueue_reset(h)) != LPA_OK) return bail(rc);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LPA_ERR_HIP);
@@ -1652,6 +1656,7 @@ int lpa_batch_create(int capacity, int k, const lpa_config *cfg_in, lpa_batch **
   b->async_mode = (cfg.flags & LPA_MODE_MASK) == LPA_MODE_ASYNC;
   b->stream = (hipStream_t)cfg.stream;
   b->check_every = cfg.check_every;
+  b->blocks_cap = cfg.move_blocks_per_cu;
   if ((rc = batch_alloc(b)) != LPA_OK) {
     batch_release(b);
     return rc;

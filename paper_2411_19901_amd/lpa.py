@@ -57,7 +57,7 @@ class LpaConfig(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("lane_max_degree", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("stream_chunk_kib", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("move_blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class LpaError(RuntimeError):
@@ -330,7 +330,8 @@ class LPA:
                  validate: bool = True, lane_max_degree: int = 0, check_every: int = 0,
                  stream=None, workspace=None, rule: str = "mg", rescan: bool = False,
                  hub_shared: bool = False, capture: bool = False, shared_vars: bool = False,
-                 stream_csr: bool = False, stream_chunk_kib: int = 0, ranked: bool = False):
+                 stream_csr: bool = False, stream_chunk_kib: int = 0, ranked: bool = False,
+                 move_blocks_per_cu: int = 0):
         import torch
 
         def usable(t):  # device memory, or pinned host memory the device maps
@@ -356,6 +357,7 @@ class LPA:
                      | (LPA_CAPTURE if capture else 0) | (LPA_STREAM_CSR if stream_csr else 0)
                      | (LPA_RANKED_LAYOUT if ranked else 0))
         cfg.stream_chunk_kib = stream_chunk_kib
+        cfg.move_blocks_per_cu = move_blocks_per_cu
         cfg.rho = rho
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -464,9 +466,11 @@ class Batch:
 
     def __init__(self, capacity: int, k: int = 8, mode: str = "det", check_every: int = 0,
                  stream=None, device=None, rule: str = "mg", rescan: bool = False,
-                 hub_shared: bool = False, capture: bool = False, shared_vars: bool = False):
+                 hub_shared: bool = False, capture: bool = False, shared_vars: bool = False,
+                 move_blocks_per_cu: int = 0):
         import torch
         cfg = lpa_config_default()
+        cfg.move_blocks_per_cu = move_blocks_per_cu
         cfg.flags = (MODES[mode] | RULES[rule] | (LPA_RESCAN if rescan else 0)
                      | (LPA_HUB_SHARED if hub_shared else 0) | (LPA_CAPTURE if capture else 0)
                      | (LPA_SHARED_VARS if shared_vars else 0))

@@ -29,7 +29,8 @@ def test_config_default():
     assert cfg.flags == lpa.LPA_MODE_DET | lpa.LPA_VALIDATE
     assert cfg.rho == 8 and not cfg.stream and cfg.lane_max_degree == 0
     assert cfg.check_every == 0 and not cfg.workspace and cfg.workspace_bytes == 0
-    assert cfg.stream_chunk_kib == 0 and list(cfg.reserved) == [0] * 3
+    assert cfg.stream_chunk_kib == 0 and list(cfg.reserved) == [0] * 2
+    assert cfg.move_blocks_per_cu == 0
 
 
 def _init(**kw):
@@ -189,6 +190,12 @@ def test_stream_csr_config():
     cfg.reserved[0] = 1
     assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg), ctypes.byref(out)) == \
         lpa.LPA_ERR_ARG
+    cfg.reserved[0] = 0
+    for blocks, code in ((-1, lpa.LPA_ERR_ARG), (65, lpa.LPA_ERR_ARG), (1, lpa.LPA_OK),
+                         (64, lpa.LPA_OK)):
+        cfg.move_blocks_per_cu = blocks
+        assert L.lpa_workspace_bytes(1000, 20000, 8, 20, ctypes.byref(cfg),
+                                     ctypes.byref(out)) == code
 
 
 def test_ranked_layout_workspace():

@@ -61,11 +61,13 @@ def test_bench_batch_and_serve_lines(monkeypatch, capsys):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "batch", "--batch-graphs", "16",
-                                      "--steps", "1", "--warmup", "1", "--capture"])
+                                      "--steps", "1", "--warmup", "1", "--capture",
+                                      "--autotune"])
     bench.main()
     d = _json_line(capsys.readouterr().out)
     assert d["unit"] == "graphs/s" and d["value"] > 0 and d["identical_labels_and_iterations"]
-    assert d["config"]["captured"] is True
+    assert d["config"]["captured"] is True and d["config"]["autotuned"] is True
+    assert d["default_shape_graphs_per_s"] > 0 and d["autotune"]["batch_ms_by_blocks"]
     assert d["cpu_baseline"]["labels_equal_gpu_batched"] is True
     monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "serve", "--requests", "12",
                                       "--serve-max-scale", "14", "--serve-loads", "1.0",
