@@ -715,7 +715,10 @@ def main():
             "avg_launch_ms": round(tmo["kernel_ms"] / max(tmo["launches"], 1), 4),
             "achieved_GBps": round(ach, 1), "frac": round(ach / HBM_PEAK_GBPS, 4),
             "scan_memory_floor_ms": round(fl, 4), "iterations": tmo["iters"][-1],
-            "modularity": round(other.modularity(), 6), "bytes_per_vertex": round(cb / g.n, 3)}
+            "modularity": round(other.modularity(), 6), "bytes_per_vertex": round(cb / g.n, 3),
+            "traffic": traffic_from_profiles(
+                kname, (workload[:-len("-ranked")] if args.ranked else workload + "-ranked"),
+                digest)}
         other.close()
     quality = (not args.no_quality and args.mode == "async" and args.rule == "mg"
                and not (args.host_csr or args.stream_csr or args.hub_shared))
