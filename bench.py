@@ -623,9 +623,13 @@ def main():
 
     floor_ms = solver.memory_floor_ms(3)
     labels = solver.labels(device=True)
-    tq = time.perf_counter()
-    q = solver.modularity()
-    mod_ms = (time.perf_counter() - tq) * 1e3
+    q = solver.modularity()  # the first call allocates the community totals
+    mod_ms = None
+    for _ in range(3):  # warm calls: k_modularity, the totals pass, four doubles back
+        tq = time.perf_counter()
+        q = solver.modularity()
+        t_q = (time.perf_counter() - tq) * 1e3
+        mod_ms = t_q if mod_ms is None else min(mod_ms, t_q)
     dn, sc = solver.trace()
     ms = solver.move_ms()
 

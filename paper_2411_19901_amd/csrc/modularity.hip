@@ -17,19 +17,25 @@
 namespace lpa {
 namespace {
 
-// tot[c] += x for every lane where `on` holds, with one atomic per distinct
-// label present in the wavefront (a converged labelling puts most vertices
-// of a wavefront in the same community).
+// tot[c] += x for every lane where `on` holds.  The labels of the first
+// active lane's community are summed across the wavefront and added with one
+// atomic (a converged labelling puts most vertices of a wavefront in one
+// community); every other lane adds its own value, so a wavefront of
+// distinct labels issues plain atomics with no cross-lane sums.
 __device__ void add_by_label(double *tot, int c, double x, bool on) {
   const int lane = threadIdx.x & (kWave - 1);
-  unsigned long long rest = __ballot(on);
-  while (rest) {
-    const int src = __ffsll((long long)rest) - 1;
-    const int cs = rl(c, src);
-    const bool mine = on && c == cs;
-    rest &= ~__ballot(mine);
-    const double s = wave_sum_d(mine ? x : 0.0);
+  const unsigned long long act = __ballot(on);
+  if (!act) return;
+  const int src = __ffsll((long long)act) - 1;
+  const int cs = rl(c, src);
+  const bool grp = on && c == cs;
+  const unsigned long long same = __ballot(grp);
+  if (same & (same - 1)) {  // two or more lanes share the first label
+    const double s = wave_sum_d(grp ? x : 0.0);
     if (lane == src) atomicAdd(&tot[cs], s);
+    if (on && !grp) atomicAdd(&tot[c], x);
+  } else if (on) {
+    atomicAdd(&tot[c], x);
   }
 }
 
