@@ -486,6 +486,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=20)
     ap.add_argument("--tol", type=float, default=0.05)
     ap.add_argument("--lane-max-degree", type=int, default=0)
+    ap.add_argument("--check-every", type=int, default=-1,
+                    help="lpa_config.check_every of the solve (-1: 1 above 5e7 entries, else 0)")
     ap.add_argument("--move-blocks-per-cu", type=int, default=0,
                     help="cap on resident move-kernel workgroups per CU (0 = all that fit)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -598,6 +600,11 @@ def main():
             f"{args.move_blocks_per_cu} ({tuned['table']})")
     free0, _ = torch.cuda.mem_get_info(dev)
     t = time.perf_counter()
+    # large graphs read the stop flag after every iteration (a host round
+    # trip of a few microseconds) rather than enqueue every remaining
+    # iteration of max_iter, whose launches cost more once converged
+    check_every = args.check_every if args.check_every >= 0 else (1 if g.nnz > 50_000_000 else 0)
+
     def make_solver(ranked):
         return lpa.LPA(rp, col, w, k=args.k, tol=args.tol, max_iter=args.max_iter,
                        mode=args.mode, lane_max_degree=args.lane_max_degree, rule=args.rule,
@@ -605,7 +612,7 @@ def main():
                        shared_vars=args.shared_vars, stream_csr=args.stream_csr,
                        stream_chunk_kib=args.stream_chunk_kib, ranked=ranked,
                        move_blocks_per_cu=args.move_blocks_per_cu,
-                       check_every=1 if g.nnz > 50_000_000 else 0, stream=stream)
+                       check_every=check_every, stream=stream)
 
     solver = make_solver(args.ranked)
     torch.cuda.synchronize()

@@ -458,6 +458,23 @@ __device__ __forceinline__ void hub_feed(const MoveArgs &a, int self, Pos beg, P
   __builtin_amdgcn_s_setprio(0);
 }
 
+// Smallest value of lanes 0..K-1 for K = 16 or 32, in every lane: rotations
+// within each 16-lane row, then the two rows' minima for K = 32.  A minimum
+// is exact, so the order of the reduction does not matter.  (For k <= 8 the
+// K independent lane reads are the shorter chain.)
+template <int K>
+__device__ __forceinline__ float slot_min(float val, int lane) {
+  static_assert(K == 16 || K == 32, "slot_min: 16 or 32 slots");
+  float t = lane < K ? val : __int_as_float(0x7f800000);
+  t = fminf(t, dpp_f<0x128>(t));  // row_ror:8
+  t = fminf(t, dpp_f<0x124>(t));  // row_ror:4
+  t = fminf(t, dpp_f<0x122>(t));  // row_ror:2
+  t = fminf(t, dpp_f<0x121>(t));  // row_ror:1
+  float m = rl_f(t, 0);
+  if constexpr (K > 16) m = fminf(m, rl_f(t, 16));
+  return m;
+}
+
 // Lane s < K holds slot s.  For each chunk every lane first finds the slot
 // whose key equals its label (at most one: keys are unique).  Entries are
 // consumed in lane order: a run of entries whose label is already a key
@@ -506,8 +523,12 @@ __device__ void hub_vertex_det(const MoveArgs &a, int p, unsigned long long &sca
       float r = xw;
       if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
         float m = xw;
+        if constexpr (K >= 16) {
+          m = fminf(m, slot_min<K>(val, lane));
+        } else {
 #pragma unroll
-        for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+          for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+        }
         if (lane < K) val = val - m;
         r = xw - m;
         z = r > 0.0f ? __ballot(lane < K && val == 0.0f) : 0ull;
@@ -931,11 +952,11 @@ __device__ __forceinline__ void record_moved_hub(const MoveArgs &a, int h, bool 
 // the lowest label.
 template <int CTRL>
 __device__ __forceinline__ int quad_dpp(int x) {
-  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+  return dpp<CTRL>(x);
 }
 template <int CTRL>
 __device__ __forceinline__ float quad_dpp_f(float x) {
-  return __int_as_float(quad_dpp<CTRL>(__float_as_int(x)));
+  return dpp_f<CTRL>(x);
 }
 constexpr int kQuadX1 = 0xB1;  // lanes (1, 0, 3, 2) of the quad
 constexpr int kQuadX2 = 0x4E;  // lanes (2, 3, 0, 1)

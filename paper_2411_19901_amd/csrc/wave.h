@@ -31,6 +31,17 @@ __device__ __forceinline__ float rl_f(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
+// DPP move across lanes (CTRL: the dpp_ctrl encoding), every row and bank
+// enabled; the source lanes are always active where these are used.
+template <int CTRL>
+__device__ __forceinline__ int dpp(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(dpp<CTRL>(__float_as_int(x)));
+}
+
 // Order LDS accesses of this wavefront: the wavefront executes its LDS
 // instructions in order, this only keeps the compiler from moving them.
 __device__ __forceinline__ void wave_lds_sync() {
