@@ -410,22 +410,32 @@ struct HubChunks {
   int lab[D];
   float x[D];  // 0 for padding and self-loops
 
-  // self: the vertex's own index as its row entries name it
+  // self: the vertex's own index as its row entries name it.  Column
+  // indices, then weights, then labels: no load waits for another of its
+  // phase, so each phase's D loads are in flight together (a weight load
+  // conditioned on its column index would wait for that index first).
   template <class Pos>
   __device__ __forceinline__ void load(const MoveArgs &a, int self, Pos sb, Pos end, int lane) {
     int c[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const Pos e = sb + d * kWave + lane;
-      c[d] = -1;
-      x[d] = 0.0f;
-      if (e < end) {
-        c[d] = __builtin_nontemporal_load(a.col + e);
-        x[d] = (c[d] == self) ? 0.0f : (a.w ? __builtin_nontemporal_load(a.w + e) : 1.0f);
+      c[d] = e < end ? __builtin_nontemporal_load(a.col + e) : -1;
+    }
+    if (a.w) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const Pos e = sb + d * kWave + lane;
+        x[d] = e < end ? __builtin_nontemporal_load(a.w + e) : 0.0f;
       }
+    } else {
+#pragma unroll
+      for (int d = 0; d < D; ++d) x[d] = 1.0f;
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) lab[d] = c[d] >= 0 ? a.C[c[d]] : 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) x[d] = (c[d] < 0 || c[d] == self) ? 0.0f : x[d];
   }
 };
 
@@ -872,17 +882,24 @@ __device__ __forceinline__ void move_body(const Launch &L) {
     }
     const MoveArgs a = make_args(d, iter);
     const int local = item - L.prefix_items[g];
-    const int hub_items = ASYNC ? 0 : a.n_hubs;
-    if (local < hub_items) {
-      if constexpr (K == 0)
-        hub_vertex_det_bm<Pos>(a, local, scanned_w, changed_w);
-      else if constexpr (SV)
-        hub_vertex_det_sv<K, Pos>(a, local, scanned_w, changed_w);
-      else
-        hub_vertex_det<K, RS, Pos>(a, local, scanned_w, changed_w);
-    } else
-      lane_units<K, ASYNC, RS, Pos, kKeepCols<K, RS, Pos, SV>>(
-          a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane, changed_w);
+    // det mode: one wavefront per hub first; async mode has none (its hubs
+    // are cut into segments, which are lane units), so the async kernels
+    // carry no hub-chain code
+    int hub_items = 0;
+    if constexpr (!ASYNC) {
+      hub_items = a.n_hubs;
+      if (local < hub_items) {
+        if constexpr (K == 0)
+          hub_vertex_det_bm<Pos>(a, local, scanned_w, changed_w);
+        else if constexpr (SV)
+          hub_vertex_det_sv<K, Pos>(a, local, scanned_w, changed_w);
+        else
+          hub_vertex_det<K, RS, Pos>(a, local, scanned_w, changed_w);
+        continue;
+      }
+    }
+    lane_units<K, ASYNC, RS, Pos, kKeepCols<K, RS, Pos, SV>>(
+        a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane, changed_w);
   }
   flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
 }
@@ -893,12 +910,15 @@ __device__ __forceinline__ void move_body(const Launch &L) {
 template <bool W>
 using PosOf = typename std::conditional<W, long long, int>::type;
 
-// One iteration's label moves (single scan) ...  With 32-bit positions and
-// up to k = 8 the kernel fits 128 registers, which keeps four wavefronts
-// per SIMD for the gathers; the other instantiations are left to the
-// compiler (forcing four would spill).
+// One iteration's label moves (single scan) ...  With 32-bit positions the
+// kernel fits 128 registers up to k = 8 and k = 16 in det mode, which keeps
+// four wavefronts per SIMD for the gathers, and 168 for k = 16 in async
+// mode (three); the other instantiations are left to the compiler.
 template <int K, bool ASYNC, bool W>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(!W && K <= 8 ? 4 : 1)))
+constexpr int kMoveWaves = W ? 1 : (K <= 8 || (K == 16 && !ASYNC)) ? 4 : K == 16 ? 3 : 1;
+
+template <int K, bool ASYNC, bool W>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMoveWaves<K, ASYNC, W>)))
 void k_move(Launch L) {
   move_body<K, ASYNC, false, PosOf<W>>(L);
 }
