@@ -182,13 +182,17 @@ __global__ void k_scan_sums(unsigned *sums, int nchunks, const unsigned *x, int 
     acc += y;
   }
   // first position of class kHubClasses (block 0) = number of hubs; first
-  // position of the isolated class = hubs + lane vertices
+  // position of the isolated class = hubs + lane vertices; from the first
+  // position of kShortClass on, the lane vertices are short
   const size_t i = (size_t)kHubClasses * nblk;
   const unsigned hubs = x[i] + sums[i / kScanChunk];
   const size_t j = (size_t)kClasses * nblk;
   const unsigned placed = x[j] + sums[j / kScanChunk];
+  const size_t q = (size_t)kShortClass * nblk;
+  const unsigned short_first = x[q] + sums[q / kScanChunk];
   totals[0] = (int)hubs;
   totals[1] = (int)(placed - hubs);
+  totals[3] = (int)(placed - (short_first > hubs ? short_first : hubs));
 }
 
 __global__ void k_scan_add(unsigned *x, size_t count, const unsigned *sums) {
@@ -1053,8 +1057,10 @@ namespace {
 // vertices, then the isolated ones): the binning kernels above, with the label buffer C[0] as their count matrix
 // (before the labels are initialised) and synchronising once for the
 // totals.
-hipError_t bin_range(lpa_handle *h, int v0, int nr, int32_t *order, int *hubs, int *lanes) {
+hipError_t bin_range(lpa_handle *h, int v0, int nr, int32_t *order, int *hubs, int *lanes,
+                     int *shorts = nullptr) {
   *hubs = *lanes = 0;
+  if (shorts) *shorts = 0;
   if (nr <= 0) return hipSuccess;
   const int nblk = (nr + kBinIds - 1) / kBinIds;
   const size_t cells = (size_t)kBinClasses * nblk;
@@ -1079,6 +1085,7 @@ hipError_t bin_range(lpa_handle *h, int v0, int nr, int32_t *order, int *hubs, i
     return e;
   *hubs = totals[0];
   *lanes = totals[1];
+  if (shorts) *shorts = totals[3];
   return hipSuccess;
 }
 
@@ -1218,6 +1225,7 @@ int stream_bin(lpa_handle *h) {
     d.order = S.order + off;
     d.n_hubs = hubs;
     d.n_lane = lanes;
+    d.n_short = 0;  // a range's lane vertices all run as staged lane units
     d.n_seg = 0;
     int nseg = 0;
     if (h->async_mode) {  // this range's hubs split into segments of lane_max entries
@@ -1499,11 +1507,15 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
 
   // degree binning (once per graph)
   if (n > 0) {
-    int hubs = 0, lanes = 0;
-    if (bin_range(h, 0, n, (int32_t *)d.order, &hubs, &lanes) != hipSuccess)
+    int hubs = 0, lanes = 0, shorts = 0;
+    if (bin_range(h, 0, n, (int32_t *)d.order, &hubs, &lanes, &shorts) != hipSuccess)
       return bail(LPA_ERR_HIP);
     d.n_hubs = hubs;
     d.n_lane = lanes;
+    // short units: single scan only (the double scan's second pass stays in
+    // the staged lane units), and not for a streamed CSR, whose ranges are
+    // binned on their own
+    d.n_short = (cfg.flags & (LPA_RESCAN | LPA_STREAM_CSR)) ? 0 : shorts;
   }
   // split every hub into segments of lane_max entries (async: the move
   // kernels' work items; both modes: modularity's)
@@ -1550,8 +1562,8 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     d.ranked = 1;
   }
   d.hub_shared = (cfg.flags & LPA_HUB_SHARED) ? 1 : 0;
-  d.items = h->async_mode ? ((d.hub_shared ? 0 : d.n_seg) + d.n_lane + kWave - 1) / kWave
-                          : d.n_hubs + (d.n_lane + kWave - 1) / kWave;
+  d.items = (int32_t)(h->async_mode ? lane_items((d.hub_shared ? 0 : d.n_seg) + d.n_lane, d.n_short)
+                                    : d.n_hubs + lane_items(d.n_lane, d.n_short));
   if (h->sm.on && (rc = stream_bin(h)) != LPA_OK) return bail(rc);
 
   // the batch of one that lpa_step / lpa_run use

@@ -29,6 +29,23 @@ constexpr int kClasses = kHubClasses + kLaneBuckets + kLaneExact;
 // then isolated ones.
 constexpr int kBinClasses = kClasses + 1;
 
+// Short units: the lane vertices of degree 1 .. kShortDeg (the last lane
+// classes of the degree order) are scanned kShortRows rows per lane, each
+// lane reading its own rows (see short_units in move.hip).
+constexpr int kShortDeg = 4;
+constexpr int kShortRows = 2;
+// Class of degree kShortDeg: the short vertices are the lane vertices from
+// its first position on.
+constexpr int kShortClass = kHubClasses + kLaneBuckets + (kLaneExact - kShortDeg);
+
+// Move-kernel work items of `units` lane units of which the last `n_short`
+// are short vertices: kWave lane units per item, then kShortRows x kWave
+// short vertices per item.
+__host__ __device__ inline int64_t lane_items(int64_t units, int64_t n_short) {
+  const int64_t per = (int64_t)kWave * kShortRows;
+  return (units - n_short + kWave - 1) / kWave + (n_short + per - 1) / per;
+}
+
 __host__ __device__ inline int octave_bucket(int d) {  // d >= 1
   const int b = 31 - __builtin_clz((unsigned)d);
   const int sub = b >= 3 ? (d >> (b - 3)) & 7 : (d << (3 - b)) & 7;
@@ -70,7 +87,7 @@ struct GraphStatus {
   int32_t iter;       // iterations run so far
   int32_t done;       // converged or max_iter reached
   int32_t err;        // validation / label-check error bits
-  int32_t totals[4];  // binning results: hubs, lane vertices, segments
+  int32_t totals[4];  // binning results: hubs, lane vertices, segments, short vertices
   int32_t pad;
   unsigned long long sink;
 };
@@ -81,6 +98,7 @@ struct GraphDesc {
   int32_t n;
   int32_t n_hubs;     // vertices of degree > seg_len
   int32_t n_lane;     // vertices of degree 1 .. seg_len
+  int32_t n_short;    // the last n_short lane vertices run as short units (degree <= kShortDeg)
   int32_t n_seg;      // async hub segments (0 in det mode)
   int32_t seg_len;    // S: longest run of CSR entries one lane scans
   int32_t max_iter;
@@ -142,6 +160,7 @@ struct MoveArgs {
   int32_t ranked;          // state indexed by degree-order position (GraphDesc::ranked)
   int32_t n_hubs;
   int32_t n_lane;
+  int32_t n_short;
   int32_t seg_len;
   int32_t n_seg;
   gptr<const int32_t> seg_hub;

@@ -739,7 +739,7 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
     beg = rb + (Pos)q * a.seg_len;
     len = (int)min((Pos)a.seg_len, (Pos)(re - beg));
     pslot = u;
-  } else if (u < a.n_seg + a.n_lane) {
+  } else if (u < a.n_seg + a.n_lane - a.n_short) {
     const int p = a.n_hubs + (u - a.n_seg);
     v = a.order[p];
     sx = state_at(a, p, v);
@@ -793,6 +793,93 @@ __device__ __forceinline__ void lane_units(const MoveArgs &a, Stage<kStageT, Pos
 }
 
 // ---------------------------------------------------------------------------
+// Short units (both modes, single scan): the last n_short lane vertices,
+// whose rows have at most kShortDeg entries.  A wavefront takes kShortRows x
+// 64 of them and every lane reads its own kShortRows rows, with no LDS stage:
+// the rows' offsets, then all their column indices, weights and labels are
+// loaded phase by phase before any sketch step.  Such rows cost little
+// bandwidth but four dependent loads each (vertex id, row offsets, columns,
+// labels), so a wavefront that waits for two rows per lane at a time keeps
+// twice the loads of a staged lane unit in flight.  Each row's entries feed
+// its sketch in CSR order with the same weights as in lane_units (the stage's
+// padding entries after a row's end are no-ops there), so det results are
+// the same.
+// q0: index of the unit's first vertex among the short vertices.
+// ---------------------------------------------------------------------------
+template <int K, bool ASYNC, class Pos>
+__device__ __forceinline__ void short_units(const MoveArgs &a, int q0, unsigned long long &scanned,
+                                            unsigned long long &changed) {
+  constexpr int R = kShortRows, D = kShortDeg;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int p0 = a.n_hubs + a.n_lane - a.n_short;  // degree-order position of the first one
+  int v[R], sx[R], cv[R], len[R];
+  bool act[R];
+  Pos beg[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = q0 + r * kWave + lane;
+    v[r] = q < a.n_short ? a.order[p0 + q] : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = q0 + r * kWave + lane;
+    sx[r] = v[r] >= 0 ? state_at(a, p0 + q, v[r]) : -1;
+    act[r] = sx[r] >= 0 && a.act_cur[sx[r]] != 0;
+    cv[r] = sx[r] >= 0 ? a.C[sx[r]] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    beg[r] = 0;
+    len[r] = 0;
+    if (act[r]) {
+      a.act_cur[sx[r]] = 0;
+      beg[r] = row_at<Pos>(a.row_ptr, v[r]);
+      len[r] = (int)(row_at<Pos>(a.row_ptr, v[r] + 1) - beg[r]);
+    }
+  }
+  int c[R][D], lab[R][D];
+  float x[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      c[r][j] = j < len[r] ? __builtin_nontemporal_load(a.col + (beg[r] + j)) : -1;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      x[r][j] = j < len[r] ? (a.w ? __builtin_nontemporal_load(a.w + (beg[r] + j)) : 1.0f) : 0.0f;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < D; ++j) lab[r][j] = c[r][j] >= 0 ? a.C[c[r][j]] : -1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    typename SketchOf<K>::type S;
+    S.clear();
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < len[r]) S.add(lab[r][j], c[r][j] == sx[r] ? 0.0f : x[r][j]);
+    const int ch = S.max_key(cv[r]);
+    const bool moved = act[r] && ch != cv[r] && (!a.pickless || ch < cv[r]);
+    if (sx[r] >= 0) {
+      if (ASYNC) {
+        if (moved) a.C[sx[r]] = ch;
+      } else {
+        a.Cn[sx[r]] = moved ? ch : cv[r];
+      }
+    }
+    changed += (unsigned long long)__popcll(__ballot(moved));
+    scanned += (unsigned long long)len[r];
+    if (moved) {
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j < len[r]) mark(a, c[r][j]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Multi-graph launches.  Work items of all graphs of a launch are numbered
 // consecutively; prefix[g] is the first item of graph g.
 // ---------------------------------------------------------------------------
@@ -822,6 +909,7 @@ __device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
   a.ranked = d.ranked;
   a.n_hubs = d.n_hubs;
   a.n_lane = d.n_lane;
+  a.n_short = d.n_short;
   a.seg_len = d.seg_len;
   a.n_seg = d.hub_shared ? 0 : d.n_seg;  // shared hubs: no segment units in k_move
   a.seg_hub = as_global(d.seg_hub);
@@ -898,8 +986,20 @@ __device__ __forceinline__ void move_body(const Launch &L) {
         continue;
       }
     }
+    // lane units (hub segments first in async mode, then whole vertices),
+    // then the short units
+    const int lane_local = local - hub_items;
+    const int units = a.n_seg + a.n_lane - a.n_short;
+    const int unit_items = (units + kWave - 1) / kWave;
+    if constexpr (!RS) {
+      if (lane_local >= unit_items) {
+        short_units<K, ASYNC, Pos>(a, (lane_local - unit_items) * (kWave * kShortRows),
+                                   scanned_lane, changed_w);
+        continue;
+      }
+    }
     lane_units<K, ASYNC, RS, Pos, kKeepCols<K, RS, Pos, SV>>(
-        a, stage[wib], (local - hub_items) * kWave + lane, scanned_lane, changed_w);
+        a, stage[wib], lane_local * kWave + lane, scanned_lane, changed_w);
   }
   flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
 }
@@ -913,9 +1013,13 @@ using PosOf = typename std::conditional<W, long long, int>::type;
 // One iteration's label moves (single scan) ...  With 32-bit positions the
 // kernel fits 128 registers up to k = 8 and k = 16 in det mode, which keeps
 // four wavefronts per SIMD for the gathers, and 168 for k = 16 in async
-// mode (three); the other instantiations are left to the compiler.
+// mode and k = 32 in det mode (three); the other instantiations are left to
+// the compiler.
 template <int K, bool ASYNC, bool W>
-constexpr int kMoveWaves = W ? 1 : (K <= 8 || (K == 16 && !ASYNC)) ? 4 : K == 16 ? 3 : 1;
+constexpr int kMoveWaves = W                                    ? 1
+                           : (K <= 8 || (K == 16 && !ASYNC))    ? 4
+                           : (K == 16 || (K == 32 && !ASYNC))   ? 3
+                                                                : 1;
 
 template <int K, bool ASYNC, bool W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMoveWaves<K, ASYNC, W>)))
