@@ -1805,6 +1805,7 @@ int modularity_into(lpa_handle *h, const int32_t *labels, double *q, double *tot
   m.order = d.order;
   m.n_hubs = d.n_hubs;
   m.n_lane = d.n_lane;
+  m.n_short = d.n_short;
   // hubs are read segment by segment (one wavefront per segment) when the
   // handle planned its segments; otherwise one wavefront per hub
   m.n_seg = h->sm.on ? 0 : h->n_segs;

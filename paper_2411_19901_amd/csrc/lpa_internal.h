@@ -195,13 +195,15 @@ hipError_t launch_finish(const Launch &L, hipStream_t s);
 
 // Modularity of one labelling (Eq. 1): vertices order[0, n_hubs) are read
 // by one wavefront per segment (or per hub without segments),
-// order[n_hubs, n_hubs + n_lane) one lane each.
+// order[n_hubs, n_hubs + n_lane) one lane each (the last n_short of them,
+// rows of at most kShortDeg entries, kShortRows rows per lane).
 // Labels must lie in [0, n).  acc[0] += 2m, acc[1] += sigma,
 // tot[c] += K_i for every vertex i labelled c.
 struct ModArgs {
   const int32_t *order;
   int32_t n_hubs;
   int32_t n_lane;
+  int32_t n_short;
   RowPtr row_ptr;
   const int32_t *col;  // ranked: degree-order positions of the neighbours
   const float *w;

@@ -172,6 +172,64 @@ __device__ void mod_hub(const ModArgs &m, int p, int v, long long rb, long long 
   ps += kv;
 }
 
+// Short rows (degree 1 .. kShortDeg, the last n_short lane vertices): each
+// lane reads its own kShortRows rows, with no stage, their column indices,
+// weights and labels loaded phase by phase, as the move kernels' short units
+// do; such rows are bound by their dependent loads, not by bandwidth.
+// q0: index of the first row among the short ones.
+__device__ void mod_short_rows(const ModArgs &m, int q0, double &k_acc, double &in_acc) {
+  constexpr int R = kShortRows, D = kShortDeg;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int p0 = m.n_hubs + m.n_lane - m.n_short;
+  const gptr<const int32_t> col = as_global(m.col);
+  const gptr<const float> wp = as_global(m.w);
+  const gptr<const int32_t> lab = as_global(m.lab);
+  int v[R], ci[R], len[R];
+  long long beg[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = q0 + r * kWave + lane;
+    v[r] = q < m.n_short ? m.order[p0 + q] : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = q0 + r * kWave + lane;
+    ci[r] = v[r] >= 0 ? lab[m.ranked ? p0 + q : v[r]] : -1;
+    beg[r] = v[r] >= 0 ? m.row_ptr[v[r]] : 0;
+    len[r] = v[r] >= 0 ? (int)(m.row_ptr[v[r] + 1] - beg[r]) : 0;
+  }
+  int c[R][D], l[R][D];
+  float x[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      c[r][j] = j < len[r] ? __builtin_nontemporal_load(col + (beg[r] + j)) : -1;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      x[r][j] = j < len[r] ? (wp ? __builtin_nontemporal_load(wp + (beg[r] + j)) : 1.0f) : 0.0f;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < D; ++j) l[r][j] = c[r][j] >= 0 ? lab[c[r][j]] : -1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double ki = 0.0, in = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (j < len[r]) {
+        ki += (double)x[r][j];
+        if (l[r][j] == ci[r]) in += (double)x[r][j];
+      }
+    }
+    k_acc += ki;
+    in_acc += in;
+    add_by_label(m.tot, ci[r], ki, v[r] >= 0 && len[r] > 0);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_modularity(ModArgs m) {
   __shared__ Stage<kStageT, long long> stage[kBlock / kWave];  // 64-bit row positions
   const int lane = threadIdx.x & (kWave - 1);
@@ -180,7 +238,9 @@ __global__ __launch_bounds__(kBlock) void k_modularity(ModArgs m) {
   const int nwaves = gridDim.x * (kBlock / kWave);
   // hub items: one per segment, or one per whole hub without segments
   const int hub_items = m.n_seg > 0 ? m.n_seg : m.n_hubs;
-  const int items = hub_items + (m.n_lane + kWave - 1) / kWave;
+  const int lane_rows = m.n_lane - m.n_short;  // staged lane rows, then the short ones
+  const int row_items = (lane_rows + kWave - 1) / kWave;
+  const int items = hub_items + (int)lane_items(m.n_lane, m.n_short);
   double k_acc = 0.0, in_acc = 0.0, ps = 0.0;
   int pc = -1;
   for (int item = wave; item < items; item += nwaves) {
@@ -196,10 +256,12 @@ __global__ __launch_bounds__(kBlock) void k_modularity(ModArgs m) {
       const long long b = m.n_seg > 0 ? rb + q * m.seg_len : rb;
       const long long e = m.n_seg > 0 ? min(b + (long long)m.seg_len, re) : re;
       mod_hub(m, h, v, b, e, k_acc, in_acc, pc, ps);
-    } else {
+    } else if (item - hub_items < row_items) {
       const int u = (item - hub_items) * kWave + lane;
-      const int v = u < m.n_lane ? m.order[m.n_hubs + u] : -1;
+      const int v = u < lane_rows ? m.order[m.n_hubs + u] : -1;
       mod_lane_rows<kStageT>(m, stage[wib], lane, m.n_hubs + u, v, k_acc, in_acc);
+    } else {
+      mod_short_rows(m, (item - hub_items - row_items) * (kWave * kShortRows), k_acc, in_acc);
     }
   }
   if (pc >= 0 && lane == 0) atomicAdd(&m.tot[pc], ps);
