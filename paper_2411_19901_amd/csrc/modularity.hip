@@ -17,26 +17,29 @@
 namespace lpa {
 namespace {
 
-// tot[c] += x for every lane where `on` holds.  The labels of the first
-// active lane's community are summed across the wavefront and added with one
-// atomic (a converged labelling puts most vertices of a wavefront in one
-// community); every other lane adds its own value, so a wavefront of
-// distinct labels issues plain atomics with no cross-lane sums.
+// tot[c] += x for every lane where `on` holds.  The lanes that share the
+// first pending lane's label are summed across the wavefront and added with
+// one atomic, and so on for the next pending label, while such groups have
+// two or more lanes (at most kCombineRounds of them); every lane left adds
+// its own value.  A converged labelling puts a wavefront's vertices in a few
+// communities, whose atomics on one address would serialise, while a
+// wavefront of distinct labels gains nothing from cross-lane sums.
+constexpr int kCombineRounds = 8;
+
 __device__ void add_by_label(double *tot, int c, double x, bool on) {
   const int lane = threadIdx.x & (kWave - 1);
-  const unsigned long long act = __ballot(on);
-  if (!act) return;
-  const int src = __ffsll((long long)act) - 1;
-  const int cs = rl(c, src);
-  const bool grp = on && c == cs;
-  const unsigned long long same = __ballot(grp);
-  if (same & (same - 1)) {  // two or more lanes share the first label
+  unsigned long long rest = __ballot(on);
+  for (int round = 0; round < kCombineRounds && rest; ++round) {
+    const int src = __ffsll((long long)rest) - 1;
+    const int cs = rl(c, src);
+    const bool grp = ((rest >> lane) & 1ull) && c == cs;
+    const unsigned long long gm = __ballot(grp);
+    if (!(gm & (gm - 1))) break;  // a group of one: no sums from here on
     const double s = wave_sum_d(grp ? x : 0.0);
     if (lane == src) atomicAdd(&tot[cs], s);
-    if (on && !grp) atomicAdd(&tot[c], x);
-  } else if (on) {
-    atomicAdd(&tot[c], x);
+    rest &= ~gm;
   }
+  if ((rest >> lane) & 1ull) atomicAdd(&tot[c], x);
 }
 
 // One step of TW entries per row (TW <= T), as in the move kernel's
