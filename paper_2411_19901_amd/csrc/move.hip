@@ -1066,14 +1066,14 @@ __device__ __forceinline__ void record_moved_hub(const MoveArgs &a, int h, bool 
   if (h < a.n_hubs) a.hub_act[h] = moved ? 1 : 0;
 }
 
-// k = 8 flat feed with the sketch spread over a hub's four-lane group:
-// lane q of the group holds slots 2q and 2q + 1, and the group's lanes
-// exchange values with quad permutes (DPP), so one sketch update is a few
-// instructions per lane instead of a pass over all eight slots.  Same
-// arithmetic and the same slot rules as LaneSketch<8>: a matching key adds
-// the weight; otherwise every slot drops by d = min(w, smallest slot) and a
-// positive residue takes the lowest free slot; heaviest slot wins, ties to
-// the lowest label.
+// Flat feed for k = 8 and 16 with the sketch spread over a hub's four-lane
+// group: lane q of the group holds slots P q .. P q + P - 1 (P = k / 4), and
+// the group's lanes exchange values with quad permutes (DPP), so one sketch
+// update is a few instructions per lane instead of a pass over all k slots.
+// Same arithmetic and the same slot rules as LaneSketch<k>: a matching key
+// adds the weight; otherwise every slot drops by d = min(w, smallest slot)
+// and a positive residue takes the lowest free slot; heaviest slot wins,
+// ties to the lowest label.
 template <int CTRL>
 __device__ __forceinline__ int quad_dpp(int x) {
   return dpp<CTRL>(x);
@@ -1085,41 +1085,53 @@ __device__ __forceinline__ float quad_dpp_f(float x) {
 constexpr int kQuadX1 = 0xB1;  // lanes (1, 0, 3, 2) of the quad
 constexpr int kQuadX2 = 0x4E;  // lanes (2, 3, 0, 1)
 
-struct QuadSketch8 {
-  int k0, k1;
-  float v0, v1;
+template <int P>
+struct QuadSketch {
+  int k[P];
+  float v[P];
   int s0;  // index of this lane's first slot
 
   __device__ __forceinline__ void clear(int sub) {
-    k0 = k1 = -1;
-    v0 = v1 = 0.0f;
-    s0 = 2 * sub;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      k[q] = -1;
+      v[q] = 0.0f;
+    }
+    s0 = P * sub;
   }
 
   __device__ __forceinline__ void add(int c, float w) {
-    const bool m0 = k0 == c, m1 = k1 == c;
-    v0 = m0 ? v0 + w : v0;
-    v1 = m1 ? v1 + w : v1;
-    int hit = (m0 || m1) ? 1 : 0;
+    bool m = false;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const bool mq = k[q] == c;
+      v[q] = mq ? v[q] + w : v[q];
+      m = m || mq;
+    }
+    int hit = m ? 1 : 0;
     hit |= quad_dpp<kQuadX1>(hit);
     hit |= quad_dpp<kQuadX2>(hit);
     if (!hit) {
-      float d = fminf(w, fminf(v0, v1));
+      float d = w;
+#pragma unroll
+      for (int q = 0; q < P; ++q) d = fminf(d, v[q]);
       d = fminf(d, quad_dpp_f<kQuadX1>(d));
       d = fminf(d, quad_dpp_f<kQuadX2>(d));
-      v0 = v0 - d;
-      v1 = v1 - d;
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q] = v[q] - d;
       const float r = w - d;
       if (r > 0.0f) {
-        int f = v0 == 0.0f ? s0 : (v1 == 0.0f ? s0 + 1 : 8);
+        int f = 4 * P;  // lowest free slot of the group
+#pragma unroll
+        for (int q = P - 1; q >= 0; --q) f = v[q] == 0.0f ? s0 + q : f;
         f = min(f, quad_dpp<kQuadX1>(f));
         f = min(f, quad_dpp<kQuadX2>(f));
-        if (f == s0) {
-          k0 = c;
-          v0 = r;
-        } else if (f == s0 + 1) {
-          k1 = c;
-          v1 = r;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          if (f == s0 + q) {
+            k[q] = c;
+            v[q] = r;
+          }
         }
       }
     }
@@ -1128,13 +1140,12 @@ struct QuadSketch8 {
   __device__ __forceinline__ int max_key(int keep) const {
     int bk = keep;
     float bv = 0.0f;
-    if (v0 > bv || (v0 == bv && v0 > 0.0f && k0 < bk)) {
-      bk = k0;
-      bv = v0;
-    }
-    if (v1 > bv || (v1 == bv && v1 > 0.0f && k1 < bk)) {
-      bk = k1;
-      bv = v1;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      if (v[q] > bv || (v[q] == bv && v[q] > 0.0f && k[q] < bk)) {
+        bk = k[q];
+        bv = v[q];
+      }
     }
     int ok = quad_dpp<kQuadX1>(bk);
     float ov = quad_dpp_f<kQuadX1>(bv);
@@ -1154,50 +1165,52 @@ struct QuadSketch8 {
 
 // Feed the partial held by lane T of the quad (its live slots in slot order)
 // into Q; a slot of weight 0 would change nothing and is skipped.
-template <int T>
-__device__ __forceinline__ void quad_feed_partial(QuadSketch8 &Q, const int *ck, const float *cw) {
+template <int T, int K>
+__device__ __forceinline__ void quad_feed_partial(QuadSketch<K / 4> &Q, const int *ck,
+                                                  const float *cw) {
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
+  for (int s = 0; s < K; ++s) {
     const int kk = quad_dpp<T * 0x55>(ck[s]);
     const float vv = quad_dpp_f<T * 0x55>(cw[s]);
     if (vv > 0.0f) Q.add(kk, vv);
   }
 }
 
-// Flat feed of one hub's np <= 64 partials (k = 8) by its four-lane group,
-// segment order; returns the merged sketch's heaviest label (keep cv).
-__device__ __forceinline__ int hub_flat_merge8(const MoveArgs &a, int p0, int np, int sub, int cv) {
-  QuadSketch8 Q;
+// Flat feed of one hub's np <= 64 partials (k = 8 or 16) by its four-lane
+// group, segment order; returns the merged sketch's heaviest label (keep cv).
+template <int K>
+__device__ __forceinline__ int hub_flat_merge(const MoveArgs &a, int p0, int np, int sub, int cv) {
+  QuadSketch<K / 4> Q;
   Q.clear(sub);
-  int ck[8], nk[8];
-  float cw[8], nv[8];
+  int ck[K], nk[K];
+  float cw[K], nv[K];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
+  for (int s = 0; s < K; ++s) {
     ck[s] = nk[s] = -1;
     cw[s] = nv[s] = 0.0f;
   }
   if (sub < np) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      ck[s] = a.part_key[(size_t)(p0 + sub) * 8 + s];
-      cw[s] = a.part_val[(size_t)(p0 + sub) * 8 + s];
+    for (int s = 0; s < K; ++s) {
+      ck[s] = a.part_key[(size_t)(p0 + sub) * K + s];
+      cw[s] = a.part_val[(size_t)(p0 + sub) * K + s];
     }
   }
   for (int b = 0; b < np; b += kHubLanes) {
     if (b + kHubLanes + sub < np) {
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        nk[s] = a.part_key[(size_t)(p0 + b + kHubLanes + sub) * 8 + s];
-        nv[s] = a.part_val[(size_t)(p0 + b + kHubLanes + sub) * 8 + s];
+      for (int s = 0; s < K; ++s) {
+        nk[s] = a.part_key[(size_t)(p0 + b + kHubLanes + sub) * K + s];
+        nv[s] = a.part_val[(size_t)(p0 + b + kHubLanes + sub) * K + s];
       }
     }
     const int nt = min(kHubLanes, np - b);
-    quad_feed_partial<0>(Q, ck, cw);
-    if (nt > 1) quad_feed_partial<1>(Q, ck, cw);
-    if (nt > 2) quad_feed_partial<2>(Q, ck, cw);
-    if (nt > 3) quad_feed_partial<3>(Q, ck, cw);
+    quad_feed_partial<0, K>(Q, ck, cw);
+    if (nt > 1) quad_feed_partial<1, K>(Q, ck, cw);
+    if (nt > 2) quad_feed_partial<2, K>(Q, ck, cw);
+    if (nt > 3) quad_feed_partial<3, K>(Q, ck, cw);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < K; ++s) {
       ck[s] = nk[s];
       cw[s] = nv[s];
     }
@@ -1266,8 +1279,8 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
     const bool small = active && np <= kWave;
     SK S;
     S.clear();
-    if constexpr (K == 8 && !RS) {
-      if (small) c = hub_flat_merge8(a, p0, np, sub, cv);
+    if constexpr ((K == 8 || K == 16) && !RS) {
+      if (small) c = hub_flat_merge<K>(a, p0, np, sub, cv);
     } else if (small) {  // np is the same on every lane of the group
       const int gbase = lane & ~(kHubLanes - 1);
       int ck[P], nk[P];
@@ -1319,7 +1332,7 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
           for (int s = 0; s < P; ++s)
             gd.hub_cand[(size_t)h * P + s] = S.val[s] > 0.0f ? S.key[s] : -1;
         }
-      } else if constexpr (K != 8) {
+      } else if constexpr (K != 8 && K != 16) {
         c = S.max_key(cv);
       }
     }
