@@ -145,6 +145,17 @@ def test_det_independent_of_bins(lane_max):
     check_det(graph("star5000"), 4, lane_max_degree=lane_max)
 
 
+@pytest.mark.parametrize("lane_max", [2, 3, 4, 5])
+@pytest.mark.parametrize("k", [1, 8])
+def test_det_short_rows_near_threshold(lane_max, k):
+    # rows of up to 4 entries below the lane threshold run two per lane
+    # without the stage: thresholds around that degree move vertices between
+    # hubs, staged lane rows and short rows without changing any result
+    check_det(graph("grid64"), k, lane_max_degree=lane_max)
+    check_det(graph("rmat12"), k, lane_max_degree=lane_max)
+    check_det(graph("rmat10-selfloops"), k, lane_max_degree=lane_max)
+
+
 def test_det_tolerances_and_limits():
     g = graph("sbm1-s1")
     check_det(g, 8, tol=0.0)
