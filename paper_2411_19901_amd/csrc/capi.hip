@@ -281,12 +281,29 @@ __global__ void k_fill_seg_hub(const int32_t *pbase, int n_hubs, int32_t *seg_hu
     for (int q = pbase[h]; q < pbase[h + 1]; ++q) seg_hub[q] = h;
 }
 
-__global__ void k_status_set(GraphStatus *st, int iter, int done) {
+__global__ void k_status_set(GraphStatus *st, int iter, int done, int fresh) {
   if (threadIdx.x == 0) {
     st->iter = iter;
     st->done = done;
     st->err = 0;
+    st->fresh = fresh;
   }
+}
+
+// *bad = 1 if some hub row (order[0, n_hubs)) does not strictly increase:
+// one wavefront per hub compares every entry with the next.
+__global__ void k_check_hub_rows(const int32_t *order, int n_hubs, RowPtr rp, const int32_t *col,
+                                 int *bad) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int nwaves = gridDim.x * blockDim.x / 64;
+  int b = 0;
+  for (int h = wave; h < n_hubs; h += nwaves) {
+    const int v = order[h];
+    const int64_t rb = rp[v], re = rp[v + 1];
+    for (int64_t e = rb + lane; e + 1 < re; e += 64) b |= col[e] >= col[e + 1] ? 1 : 0;
+  }
+  if (__ballot(b != 0) != 0ull && lane == 0) atomicOr(bad, 1);
 }
 
 // lpa_reset of every graph of a table: blockIdx.y (strided) picks the graph,
@@ -312,6 +329,7 @@ __global__ void k_batch_reset(const GraphDesc *d, int G) {
         gd.st->iter = 0;
         gd.st->done = (gd.n == 0 || gd.max_iter == 0) ? 1 : 0;
         gd.st->err = 0;
+        gd.st->fresh = 1;
       }
     }
   }
@@ -688,7 +706,7 @@ int enqueue_reset(lpa_handle *h) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(T)), dim3(kAuxBlock), 0, h->stream,
                      h->desc.scanned, T);
   const bool done0 = (n == 0 || h->max_iter == 0);
-  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, 0, done0 ? 1 : 0);
+  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, 0, done0 ? 1 : 0, 1);
   LAUNCH_TRY(h, "reset kernels");
   h->iter = 0;
   h->finished = done0;
@@ -1490,7 +1508,7 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
     d.hub_cand = (int32_t *)(base + Ly.hcand);
   }
 
-  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, 0, 0);
+  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, 0, 0, 0);
   if (hipGetLastError() != hipSuccess) return bail(LPA_ERR_HIP);
   if (n > 0 && (cfg.flags & LPA_VALIDATE)) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for(h->nnz > n ? (size_t)h->nnz : (size_t)n)),
@@ -1545,6 +1563,22 @@ int lpa_init(const lpa_graph *g, const float *weights, int k, double tol, int ma
       d.part_key = (int32_t *)h->part_block;
       d.part_val = (float *)((char *)h->part_block + half);
     }
+  }
+  // det mode: at iteration 0 the hub chains may skip their slot lookups when
+  // no hub row repeats a neighbour (checked on the column indices in device
+  // memory; otherwise the general chain runs)
+  if (!h->async_mode && !streamed && d.n_hubs > 0 && h->nnz > 0 &&
+      pointer_location(h->col) == LPA_PTR_DEVICE) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, h->stream, &h->st->totals[3], 1);
+    hipLaunchKernelGGL(k_check_hub_rows, dim3(grid_for(d.n_hubs, 4, 4096)), dim3(256), 0,
+                       h->stream, d.order, d.n_hubs, h->row_ptr, h->col, &h->st->totals[3]);
+    int bad = 1;
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&bad, &h->st->totals[3], sizeof(int), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return bail(LPA_ERR_HIP);
+    d.hub_rows_distinct = bad ? 0 : 1;
   }
   // ranked layout: every vertex's state moves to its degree-order position,
   // and the column indices are rewritten as positions (C[0] holds the
@@ -1975,7 +2009,9 @@ int lpa_set_state(lpa_handle *h, const int32_t *labels, const uint8_t *unprocess
     LAUNCH_TRY(h, "state restore");
   }
   const bool fin = (n == 0 || iteration >= h->max_iter);
-  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, iteration, fin ? 1 : 0);
+  // labels restored from the caller are not the initial ones, even at iteration 0
+  hipLaunchKernelGGL(k_status_set, dim3(1), dim3(64), 0, h->stream, h->st, iteration, fin ? 1 : 0,
+                     0);
   LAUNCH_TRY(h, "state restore");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   h->iter = iteration;

@@ -88,7 +88,7 @@ struct GraphStatus {
   int32_t done;       // converged or max_iter reached
   int32_t err;        // validation / label-check error bits
   int32_t totals[4];  // binning results: hubs, lane vertices, segments, short vertices
-  int32_t pad;
+  int32_t fresh;      // 1: the labels are the initial ones (reset, no lpa_set_state since)
   unsigned long long sink;
 };
 
@@ -122,6 +122,10 @@ struct GraphDesc {
   float *part_val;           // [n_seg * k]
   int32_t *hub_cand;         // [n_hubs * k] double-scan candidates (-1: none)
   int32_t hub_shared;        // 1: hubs use one shared sketch each (LPA_HUB_SHARED)
+  // det: 1 when every hub row names each neighbour at most once (its column
+  // indices strictly increase; checked at lpa_init), so that at iteration 0
+  // from the initial labels every hub entry carries a label of its own
+  int32_t hub_rows_distinct;
   unsigned long long *dN;       // [max_iter] changed vertices per iteration
   unsigned long long *scanned;  // [max_iter] CSR entries scanned per iteration
   GraphStatus *st;
@@ -170,6 +174,9 @@ struct MoveArgs {
   gptr<float> part_val;
   int32_t iter;
   int32_t pickless;
+  // det iteration 0 from the initial labels with duplicate-free hub rows:
+  // every hub entry is a label no key holds (see GraphDesc::hub_rows_distinct)
+  int32_t fresh_hubs;
 };
 
 // Kernel selector: k slots of the weighted Misra-Gries sketch, or 0 for the

@@ -507,54 +507,92 @@ __device__ void hub_vertex_det(const MoveArgs &a, int p, unsigned long long &sca
   const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
   int key = -1;
   float val = 0.0f;
-  hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
-    int slot = -1;  // the slot holding this lane's label, if any
+  if (a.fresh_hubs) {
+    // Iteration 0 from the initial labels on a row without repeated
+    // neighbours: every entry's label differs from every key (live or
+    // stale), so every entry takes the step for a new label, and the free
+    // slots change only here: they are tracked in a scalar mask, with no
+    // slot lookups and no runs of hits.  The same steps as below.
+    unsigned long long z = K >= 64 ? ~0ull : ((1ull << K) - 1ull);  // all slots free
+    hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
+      unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
+      while (pend) {
+        const int j = __ffsll((long long)pend) - 1;
+        pend &= pend - 1;
+        const int c = rl(lab, j);
+        const float xw = rl_f(x, j);
+        float r = xw;
+        if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
+          float m = xw;
+          if constexpr (K >= 16) {
+            m = fminf(m, slot_min<K>(val, lane));
+          } else {
 #pragma unroll
-    for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
-    unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
-    while (pend) {
-      const unsigned long long missm = __ballot(slot < 0) & pend;
-      // entries before the first miss only add to existing slots
-      unsigned long long run = missm ? (pend & ((missm & (~missm + 1)) - 1)) : pend;
-      pend &= ~run;
-      while (run) {
-        const int h = __ffsll((long long)run) - 1;
-        run &= run - 1;
-        const int sh = rl(slot, h);
-        const float xh = rl_f(x, h);
-        val = (lane == sh) ? val + xh : val;
-      }
-      if (!missm) break;
-      const int jm = __ffsll((long long)missm) - 1;
-      pend &= ~(1ull << jm);
-      const int c = rl(lab, jm);
-      const float xw = rl_f(x, jm);
-      unsigned long long z = __ballot(lane < K && val == 0.0f);
-      float r = xw;
-      if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
-        float m = xw;
-        if constexpr (K >= 16) {
-          m = fminf(m, slot_min<K>(val, lane));
-        } else {
-#pragma unroll
-          for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+            for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+          }
+          if (lane < K) val = val - m;
+          r = xw - m;
+          z = __ballot(lane < K && val == 0.0f);
+          if (!(r > 0.0f)) continue;
         }
-        if (lane < K) val = val - m;
-        r = xw - m;
-        z = r > 0.0f ? __ballot(lane < K && val == 0.0f) : 0ull;
-      }
-      if (z) {  // the (residue of the) pair takes a free slot
-        const int s = __ffsll((long long)z) - 1;
-        const int old = rl(key, s);
+        const int s = __ffsll((long long)z) - 1;  // the lowest free slot
+        z &= z - 1;
         if (lane == s) {
           key = c;
           val = r;
         }
-        slot = (lab == old) ? -1 : slot;
-        slot = (lab == c) ? s : slot;
       }
-    }
-  });
+    });
+  } else {
+    hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
+      int slot = -1;  // the slot holding this lane's label, if any
+#pragma unroll
+      for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
+      unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
+      while (pend) {
+        const unsigned long long missm = __ballot(slot < 0) & pend;
+        // entries before the first miss only add to existing slots
+        unsigned long long run = missm ? (pend & ((missm & (~missm + 1)) - 1)) : pend;
+        pend &= ~run;
+        while (run) {
+          const int h = __ffsll((long long)run) - 1;
+          run &= run - 1;
+          const int sh = rl(slot, h);
+          const float xh = rl_f(x, h);
+          val = (lane == sh) ? val + xh : val;
+        }
+        if (!missm) break;
+        const int jm = __ffsll((long long)missm) - 1;
+        pend &= ~(1ull << jm);
+        const int c = rl(lab, jm);
+        const float xw = rl_f(x, jm);
+        unsigned long long z = __ballot(lane < K && val == 0.0f);
+        float r = xw;
+        if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
+          float m = xw;
+          if constexpr (K >= 16) {
+            m = fminf(m, slot_min<K>(val, lane));
+          } else {
+#pragma unroll
+            for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+          }
+          if (lane < K) val = val - m;
+          r = xw - m;
+          z = r > 0.0f ? __ballot(lane < K && val == 0.0f) : 0ull;
+        }
+        if (z) {  // the (residue of the) pair takes a free slot
+          const int s = __ffsll((long long)z) - 1;
+          const int old = rl(key, s);
+          if (lane == s) {
+            key = c;
+            val = r;
+          }
+          slot = (lab == old) ? -1 : slot;
+          slot = (lab == c) ? s : slot;
+        }
+      }
+    });
+  }
   if constexpr (RS) {
     // double scan: the live slots' labels are re-weighted exactly, each
     // slot's entries added in CSR order by the slot's lane
@@ -919,6 +957,7 @@ __device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
   a.part_val = as_global(d.part_val);
   a.iter = iter;
   a.pickless = (d.rho > 0 && iter % d.rho == 0) ? 1 : 0;
+  a.fresh_hubs = (iter == 0 && d.hub_rows_distinct && d.st->fresh) ? 1 : 0;
   return a;
 }
 

@@ -156,6 +156,43 @@ def test_det_short_rows_near_threshold(lane_max, k):
     check_det(graph("rmat10-selfloops"), k, lane_max_degree=lane_max)
 
 
+def test_det_first_iteration_from_restored_labels():
+    # a state restored at iteration 0 is not the initial labelling: hub rows
+    # then see repeated labels and must take the general chain (the first
+    # iteration's shortcut for distinct labels would be wrong here)
+    g = graph("rmat14")
+    rng = np.random.default_rng(14)
+    lab0 = rng.integers(0, 40, g.n).astype(np.int32)
+    act0 = np.ones(g.n, np.uint8)
+    rp, col, w = to_dev(g)
+    for lane_max in (16, 0):
+        s = lpa.LPA(rp, col, w, k=8, lane_max_degree=lane_max)
+        s.set_state(lab0, act0, 0)
+        s.step()
+        got = s.labels(device=False)
+        s.close()
+        ref, _, _, _ = oracle.lpa_move(g.row_ptr, g.col, g.w, 8, True, lab0, act0)
+        assert np.array_equal(got, ref), (lane_max, np.nonzero(got != ref)[0][:10])
+
+
+def test_det_hub_rows_with_repeated_neighbours():
+    # a multigraph: hub rows that name a neighbour several times keep the
+    # general chain at iteration 0 (labels repeat within the row)
+    base = star(3000)
+    rows = [list(base.col[base.row_ptr[i]:base.row_ptr[i + 1]]) for i in range(base.n)]
+    rows[0] = sorted(rows[0] + rows[0][::7])  # the hub repeats every 7th leaf
+    for j in rows[0][::7]:
+        rows[j] = sorted(rows[j] + [0])
+    rp = np.zeros(base.n + 1, np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([c for r in rows for c in r], np.int32)
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0.5, 1.0, len(col)).astype(np.float32)
+    g = inputs.Graph(rp, col, w, "star3000-repeats")
+    for k in (2, 8):
+        check_det(g, k, lane_max_degree=64)
+
+
 def test_det_tolerances_and_limits():
     g = graph("sbm1-s1")
     check_det(g, 8, tol=0.0)
