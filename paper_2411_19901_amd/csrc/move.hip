@@ -485,11 +485,157 @@ __device__ __forceinline__ float slot_min(float val, int lane) {
   return m;
 }
 
+// Adds the entries `run` (lanes whose label is a key, slot: that key's slot)
+// to their slots.  UNIT: every such entry weighs 1 and every slot value is
+// an integer below 2^24 (unit weights on a row shorter than 2^24 entries),
+// so each slot takes its count of entries at once, exactly the sum that
+// adding them one by one in CSR order gives; otherwise one entry at a time
+// in lane order, with scalar lane indices and no cross-lane votes.
+template <bool UNIT>
+__device__ __forceinline__ void add_hits(unsigned long long run, int slot, float x, int lane,
+                                         float &val) {
+  if constexpr (UNIT) {
+    while (run) {
+      const int s = rl(slot, __ffsll((long long)run) - 1);
+      const unsigned long long ms = __ballot(slot == s) & run;
+      run &= ~ms;
+      val = (lane == s) ? val + (float)(int)__popcll(ms) : val;
+    }
+  } else {
+    while (run) {
+      const int h = __ffsll((long long)run) - 1;
+      run &= run - 1;
+      const int sh = rl(slot, h);
+      const float xh = rl_f(x, h);
+      val = (lane == sh) ? val + xh : val;
+    }
+  }
+}
+
+// Iteration 0 from the initial labels on a row without repeated neighbours
+// (MoveArgs::fresh_hubs): every entry's label differs from every key (live
+// or stale), so every entry takes the step for a new label, and the free
+// slots change only here: they are tracked in a scalar mask, with no slot
+// lookups and no runs of hits.  The same steps as det_chain, UNIT likewise.
+template <int K, bool UNIT, class Pos>
+__device__ __forceinline__ void det_fresh(const MoveArgs &a, int x0, Pos beg, Pos end, int lane,
+                                          int &key, float &val) {
+  unsigned long long z = K >= 64 ? ~0ull : ((1ull << K) - 1ull);  // all slots free
+  hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
+    unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
+    while (pend) {
+      const int j = __ffsll((long long)pend) - 1;
+      pend &= pend - 1;
+      const int c = rl(lab, j);
+      float r;
+      if constexpr (UNIT) {
+        if (z == 0ull) {  // every slot live: each loses 1, the entry is used up
+          if (lane < K) val = val - 1.0f;
+          z = __ballot(lane < K && val == 0.0f);
+          continue;
+        }
+        r = 1.0f;
+      } else {
+        const float xw = rl_f(x, j);
+        r = xw;
+        if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
+          float m = xw;
+          if constexpr (K >= 16) {
+            m = fminf(m, slot_min<K>(val, lane));
+          } else {
+#pragma unroll
+            for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+          }
+          if (lane < K) val = val - m;
+          r = xw - m;
+          z = __ballot(lane < K && val == 0.0f);
+          if (!(r > 0.0f)) continue;
+        }
+      }
+      const int s = __ffsll((long long)z) - 1;  // the lowest free slot
+      z &= z - 1;
+      key = (lane == s) ? c : key;  // selects, not a branch on the lane
+      val = (lane == s) ? r : val;
+    }
+  });
+}
+
+// The sketch of one hub row in det mode after iteration 0 (see
+// hub_vertex_det), lane s < K holding slot s in key / val.  UNIT (see
+// add_hits): every slot value is an integer, so when every slot is live
+// each holds at least 1 and the entry's decrement, min(1, smallest slot),
+// is 1: every slot loses 1 and nothing is left to place.
+template <int K, bool UNIT, class Pos>
+__device__ __forceinline__ void det_chain(const MoveArgs &a, int x0, Pos beg, Pos end, int lane,
+                                          int &key, float &val) {
+  hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
+    int slot = -1;  // the slot holding this lane's label, if any
+#pragma unroll
+    for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
+    unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
+    while (pend) {
+      const unsigned long long missm = __ballot(slot < 0) & pend;
+      // entries before the first miss only add to existing slots
+      const unsigned long long run = missm ? (pend & ((missm & (~missm + 1)) - 1)) : pend;
+      pend &= ~run;
+      add_hits<UNIT>(run, slot, x, lane, val);
+      if (!missm) break;
+      const int jm = __ffsll((long long)missm) - 1;
+      pend &= ~(1ull << jm);
+      const int c = rl(lab, jm);
+      unsigned long long z = __ballot(lane < K && val == 0.0f);
+      float r;
+      if constexpr (UNIT) {
+        if (z == 0ull) {  // every slot live: each loses 1, the entry is used up
+          if (lane < K) val = val - 1.0f;
+          continue;
+        }
+        r = 1.0f;
+      } else {
+        const float xw = rl_f(x, jm);
+        r = xw;
+        if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
+          float m = xw;
+          if constexpr (K >= 16) {
+            m = fminf(m, slot_min<K>(val, lane));
+          } else {
+#pragma unroll
+            for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
+          }
+          if (lane < K) val = val - m;
+          r = xw - m;
+          z = r > 0.0f ? __ballot(lane < K && val == 0.0f) : 0ull;
+        }
+      }
+      if (z) {  // the (residue of the) pair takes a free slot
+        const int s = __ffsll((long long)z) - 1;
+        const int old = rl(key, s);
+        key = (lane == s) ? c : key;
+        val = (lane == s) ? r : val;
+        slot = (lab == old) ? -1 : slot;
+        slot = (lab == c) ? s : slot;
+      }
+    }
+  });
+}
+
+// Double scan: the labels of key (-1: none) re-weighted exactly, each slot's
+// entries added in CSR order by the slot's lane (val starts at 0).
+template <int K, bool UNIT, class Pos>
+__device__ __forceinline__ void det_rescan(const MoveArgs &a, int x0, Pos beg, Pos end, int lane,
+                                           const int key, float &val) {
+  hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
+    int slot = -1;
+#pragma unroll
+    for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
+    add_hits<UNIT>(__ballot(slot >= 0 && lane < cnt && x > 0.0f), slot, x, lane, val);
+  });
+}
+
 // Lane s < K holds slot s.  For each chunk every lane first finds the slot
 // whose key equals its label (at most one: keys are unique).  Entries are
 // consumed in lane order: a run of entries whose label is already a key
-// only adds weights to those slots, so it is applied entry by entry with
-// scalar lane indices and no cross-lane votes; the first entry without a
+// only adds weights to those slots (add_hits); the first entry without a
 // key takes the full sketch step, after which only the lanes whose label
 // was the replaced key or is the new key change their slot.
 // p: the vertex's degree-order position.
@@ -507,110 +653,29 @@ __device__ void hub_vertex_det(const MoveArgs &a, int p, unsigned long long &sca
   const Pos beg = rfl_as(row_at<Pos>(a.row_ptr, v)), end = rfl_as(row_at<Pos>(a.row_ptr, v + 1));
   int key = -1;
   float val = 0.0f;
-  if (a.fresh_hubs) {
-    // Iteration 0 from the initial labels on a row without repeated
-    // neighbours: every entry's label differs from every key (live or
-    // stale), so every entry takes the step for a new label, and the free
-    // slots change only here: they are tracked in a scalar mask, with no
-    // slot lookups and no runs of hits.  The same steps as below.
-    unsigned long long z = K >= 64 ? ~0ull : ((1ull << K) - 1ull);  // all slots free
-    hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
-      unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
-      while (pend) {
-        const int j = __ffsll((long long)pend) - 1;
-        pend &= pend - 1;
-        const int c = rl(lab, j);
-        const float xw = rl_f(x, j);
-        float r = xw;
-        if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
-          float m = xw;
-          if constexpr (K >= 16) {
-            m = fminf(m, slot_min<K>(val, lane));
-          } else {
-#pragma unroll
-            for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
-          }
-          if (lane < K) val = val - m;
-          r = xw - m;
-          z = __ballot(lane < K && val == 0.0f);
-          if (!(r > 0.0f)) continue;
-        }
-        const int s = __ffsll((long long)z) - 1;  // the lowest free slot
-        z &= z - 1;
-        if (lane == s) {
-          key = c;
-          val = r;
-        }
+  // Unit weights (see add_hits).  The double-scan kernels keep the general
+  // chains only: more copies of the chunk loop there put its chunk buffers
+  // in scratch memory.
+  const bool unit = !RS && !a.w && (long long)(end - beg) < (1ll << 24);
+  if (unit) {
+    if constexpr (!RS) {
+      if (a.fresh_hubs) {
+        det_fresh<K, true>(a, x0, beg, end, lane, key, val);
+      } else {
+        det_chain<K, true>(a, x0, beg, end, lane, key, val);
       }
-    });
+    }
+  } else if (a.fresh_hubs) {
+    det_fresh<K, false>(a, x0, beg, end, lane, key, val);
   } else {
-    hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
-      int slot = -1;  // the slot holding this lane's label, if any
-#pragma unroll
-      for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
-      unsigned long long pend = __ballot(lane < cnt && x > 0.0f);
-      while (pend) {
-        const unsigned long long missm = __ballot(slot < 0) & pend;
-        // entries before the first miss only add to existing slots
-        unsigned long long run = missm ? (pend & ((missm & (~missm + 1)) - 1)) : pend;
-        pend &= ~run;
-        while (run) {
-          const int h = __ffsll((long long)run) - 1;
-          run &= run - 1;
-          const int sh = rl(slot, h);
-          const float xh = rl_f(x, h);
-          val = (lane == sh) ? val + xh : val;
-        }
-        if (!missm) break;
-        const int jm = __ffsll((long long)missm) - 1;
-        pend &= ~(1ull << jm);
-        const int c = rl(lab, jm);
-        const float xw = rl_f(x, jm);
-        unsigned long long z = __ballot(lane < K && val == 0.0f);
-        float r = xw;
-        if (z == 0ull) {  // every slot live: decrement by d = min(w, smallest slot)
-          float m = xw;
-          if constexpr (K >= 16) {
-            m = fminf(m, slot_min<K>(val, lane));
-          } else {
-#pragma unroll
-            for (int s = 0; s < K; ++s) m = fminf(m, rl_f(val, s));
-          }
-          if (lane < K) val = val - m;
-          r = xw - m;
-          z = r > 0.0f ? __ballot(lane < K && val == 0.0f) : 0ull;
-        }
-        if (z) {  // the (residue of the) pair takes a free slot
-          const int s = __ffsll((long long)z) - 1;
-          const int old = rl(key, s);
-          if (lane == s) {
-            key = c;
-            val = r;
-          }
-          slot = (lab == old) ? -1 : slot;
-          slot = (lab == c) ? s : slot;
-        }
-      }
-    });
+    det_chain<K, false>(a, x0, beg, end, lane, key, val);
   }
   if constexpr (RS) {
     // double scan: the live slots' labels are re-weighted exactly, each
     // slot's entries added in CSR order by the slot's lane
     key = val > 0.0f ? key : -1;
     val = 0.0f;
-    hub_feed(a, x0, beg, end, lane, [&](int lab, float x, int cnt) {
-      int slot = -1;
-#pragma unroll
-      for (int s = 0; s < K; ++s) slot = (lab == rl(key, s)) ? s : slot;
-      unsigned long long pend = __ballot(slot >= 0 && lane < cnt && x > 0.0f);
-      while (pend) {
-        const int h = __ffsll((long long)pend) - 1;
-        pend &= pend - 1;
-        const int sh = rl(slot, h);
-        const float xh = rl_f(x, h);
-        val = (lane == sh) ? val + xh : val;
-      }
-    });
+    det_rescan<K, false>(a, x0, beg, end, lane, key, val);
   }
   // heaviest live slot, ties to the lowest label; keep when empty
   int bk = cv;
