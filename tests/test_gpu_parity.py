@@ -175,6 +175,17 @@ def test_det_first_iteration_from_restored_labels():
         assert np.array_equal(got, ref), (lane_max, np.nonzero(got != ref)[0][:10])
 
 
+@pytest.mark.parametrize("lane_max", [1, 8])
+@pytest.mark.parametrize("k", [1, 4, 8, 16, 32])
+def test_det_unit_weight_hub_chain(lane_max, k):
+    # unit weights: hub rows add runs of hits to their slots as counts and
+    # take full-sketch decrements of exactly 1; low thresholds send nearly
+    # every vertex of these converging graphs through that chain, whose
+    # later iterations are mostly hits
+    check_det(graph("sbm1-s1"), k, lane_max_degree=lane_max)
+    check_det(graph("rmat12"), k, lane_max_degree=lane_max)
+
+
 def test_det_hub_rows_with_repeated_neighbours():
     # a multigraph: hub rows that name a neighbour several times keep the
     # general chain at iteration 0 (labels repeat within the row)
@@ -189,8 +200,10 @@ def test_det_hub_rows_with_repeated_neighbours():
     rng = np.random.default_rng(3)
     w = rng.uniform(0.5, 1.0, len(col)).astype(np.float32)
     g = inputs.Graph(rp, col, w, "star3000-repeats")
+    gu = inputs.Graph(rp, col, None, "star3000-repeats-unit")  # runs of hits as counts
     for k in (2, 8):
         check_det(g, k, lane_max_degree=64)
+        check_det(gu, k, lane_max_degree=64)
 
 
 def test_det_tolerances_and_limits():
