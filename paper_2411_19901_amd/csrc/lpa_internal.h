@@ -71,6 +71,19 @@ __host__ __device__ __forceinline__ gptr<T> as_global(T *p) {
   return (gptr<T>)p;
 }
 
+// Launch tables that no kernel writes while it runs (the per-graph prefix
+// sums and descriptors, and each graph's status outside the stop test,
+// which writes it in a launch of its own): typed as the constant address
+// space, so that reads at uniform addresses are scalar loads served by the
+// scalar cache rather than vector-memory round trips.
+#define LPA_CONST __attribute__((address_space(4)))
+template <class T>
+using kptr = const T LPA_CONST *;
+template <class T>
+__host__ __device__ __forceinline__ kptr<T> as_const(const T *p) {
+  return (kptr<T>)p;
+}
+
 // CSR row offsets, 32- or 64-bit: exactly one pointer is set for a graph
 // with vertices.  The choice is the same for every vertex of a graph, so
 // the test is a uniform branch.

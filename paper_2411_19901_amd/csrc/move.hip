@@ -986,7 +986,8 @@ __device__ __forceinline__ void short_units(const MoveArgs &a, int q0, unsigned 
 // Multi-graph launches.  Work items of all graphs of a launch are numbered
 // consecutively; prefix[g] is the first item of graph g.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int find_graph(const int32_t *prefix, int G, int item) {
+__device__ __forceinline__ int find_graph(const int32_t *prefix_, int G, int item) {
+  const kptr<int32_t> prefix = as_const(prefix_);
   int lo = 0, hi = G;  // prefix[lo] <= item < prefix[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -998,10 +999,22 @@ __device__ __forceinline__ int find_graph(const int32_t *prefix, int G, int item
   return lo;
 }
 
-__device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
+// Status of graph g for the kernels other than the stop test (k_finish, the
+// only writer, runs in a launch of its own), through the scalar cache.
+__device__ __forceinline__ kptr<GraphStatus> status_of(const Launch &L, int g) {
+  return as_const(as_const(L.d)[g].st);
+}
+
+// Descriptor of graph g, through the scalar cache (the table is written
+// only by the host, before the launches).
+using DescRef = const GraphDesc LPA_CONST &;
+__device__ __forceinline__ DescRef desc_of(const Launch &L, int g) { return as_const(L.d)[g]; }
+
+__device__ __forceinline__ MoveArgs make_args(DescRef d, int iter) {
   MoveArgs a;
   a.n = d.n;
-  a.row_ptr = d.row_ptr;
+  a.row_ptr.p32 = d.row_ptr.p32;
+  a.row_ptr.p64 = d.row_ptr.p64;
   a.col = as_global(d.col);
   a.w = as_global(d.w);
   a.C = as_global(d.C[iter & 1]);
@@ -1022,7 +1035,7 @@ __device__ __forceinline__ MoveArgs make_args(const GraphDesc &d, int iter) {
   a.part_val = as_global(d.part_val);
   a.iter = iter;
   a.pickless = (d.rho > 0 && iter % d.rho == 0) ? 1 : 0;
-  a.fresh_hubs = (iter == 0 && d.hub_rows_distinct && d.st->fresh) ? 1 : 0;
+  a.fresh_hubs = (iter == 0 && d.hub_rows_distinct && as_const(d.st)->fresh) ? 1 : 0;
   return a;
 }
 
@@ -1063,9 +1076,10 @@ __device__ __forceinline__ void move_body(const Launch &L) {
   unsigned long long *cdN = nullptr, *csc = nullptr;
   for (int item = wave; item < L.total_items; item += nwaves) {
     const int g = rfl(find_graph(L.prefix_items, L.G, item));
-    const GraphDesc &d = L.d[g];
-    if (d.st->done) continue;
-    const int iter = d.st->iter;
+    const kptr<GraphStatus> st = status_of(L, g);
+    if (st->done) continue;
+    const int iter = st->iter;
+    DescRef d = desc_of(L, g);
     if (g != cur) {
       flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
       cur = g;
@@ -1073,7 +1087,7 @@ __device__ __forceinline__ void move_body(const Launch &L) {
       csc = d.scanned + iter;
     }
     const MoveArgs a = make_args(d, iter);
-    const int local = item - L.prefix_items[g];
+    const int local = item - as_const(L.prefix_items)[g];
     // det mode: one wavefront per hub first; async mode has none (its hubs
     // are cut into segments, which are lane units), so the async kernels
     // carry no hub-chain code
@@ -1330,7 +1344,7 @@ __device__ __forceinline__ int hub_flat_merge(const MoveArgs &a, int p0, int np,
 __device__ __forceinline__ int merge_hub(int it, int grp, int ni) { return grp * ni + it; }
 
 __device__ __forceinline__ int merge_items(const Launch &L, int g) {
-  return L.prefix_merge[g + 1] - L.prefix_merge[g];
+  return as_const(L.prefix_merge)[g + 1] - as_const(L.prefix_merge)[g];
 }
 
 // Merge the partial sketches of every active hub (Section 4.3).  A wavefront
@@ -1359,16 +1373,17 @@ __device__ __forceinline__ void hub_merge_body(const Launch &L) {
   constexpr int P = slots_of(K);
   for (int item = wave; item < L.total_merge; item += nwaves) {
     const int g = rfl(find_graph(L.prefix_merge, L.G, item));
-    const GraphDesc &gd = L.d[g];
-    if (gd.st->done) continue;
-    const int iter = gd.st->iter;
+    const kptr<GraphStatus> st = status_of(L, g);
+    if (st->done) continue;
+    const int iter = st->iter;
+    DescRef gd = desc_of(L, g);
     if (g != cur) {
       flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
       cur = g;
       cdN = gd.dN + iter;
     }
     const MoveArgs a = make_args(gd, iter);
-    const int it = item - L.prefix_merge[g], ni = rfl(merge_items(L, g));
+    const int it = item - as_const(L.prefix_merge)[g], ni = rfl(merge_items(L, g));
     const int h = merge_hub(it, lane / kHubLanes, ni);
     int x = -1, p0 = 0, np = 0, cv = 0;  // x: the hub's state index
     bool active = false;
@@ -1511,10 +1526,11 @@ __global__ __launch_bounds__(kBlock) void k_hub_rescan(Launch L) {
   const int nwaves = gridDim.x * (kBlock / kWave);
   for (int item = wave; item < L.total_segs; item += nwaves) {
     const int g = rfl(find_graph(L.prefix_segs, L.G, item));
-    const GraphDesc &gd = L.d[g];
-    if (gd.st->done) continue;
-    const MoveArgs a = make_args(gd, gd.st->iter);
-    const int u = item - L.prefix_segs[g];
+    const kptr<GraphStatus> st = status_of(L, g);
+    if (st->done) continue;
+    DescRef gd = desc_of(L, g);
+    const MoveArgs a = make_args(gd, st->iter);
+    const int u = item - as_const(L.prefix_segs)[g];
     const int h = a.seg_hub[u];
     if (a.hub_act[h] == 0) continue;
     const int v = a.order[h], self = state_at(a, h, v);
@@ -1572,16 +1588,17 @@ __global__ __launch_bounds__(kBlock) void k_hub_pick(Launch L) {
   unsigned long long *cdN = nullptr;
   for (int item = wave; item < L.total_merge; item += nwaves) {
     const int g = rfl(find_graph(L.prefix_merge, L.G, item));
-    const GraphDesc &gd = L.d[g];
-    if (gd.st->done) continue;
-    const int iter = gd.st->iter;
+    const kptr<GraphStatus> st = status_of(L, g);
+    if (st->done) continue;
+    const int iter = st->iter;
+    DescRef gd = desc_of(L, g);
     if (g != cur) {
       flush_counts(cdN, cdN, zero_lane, zero_w, changed_w);
       cur = g;
       cdN = gd.dN + iter;
     }
     const MoveArgs a = make_args(gd, iter);
-    const int it = item - L.prefix_merge[g], ni = rfl(merge_items(L, g));
+    const int it = item - as_const(L.prefix_merge)[g], ni = rfl(merge_items(L, g));
     const int h = merge_hub(it, lane / kHubLanes, ni);
     int x = -1, p0 = 0, np = 0, cv = 0;  // x: the hub's state index
     bool active = false;
@@ -1649,10 +1666,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_mark(Launch L) {
   const int nwaves = gridDim.x * (kBlock / kWave);
   for (int item = wave; item < L.total_segs; item += nwaves) {
     const int g = rfl(find_graph(L.prefix_segs, L.G, item));
-    const GraphDesc &gd = L.d[g];
-    if (gd.st->done) continue;
-    const MoveArgs a = make_args(gd, gd.st->iter);
-    const int u = item - L.prefix_segs[g];
+    const kptr<GraphStatus> st = status_of(L, g);
+    if (st->done) continue;
+    const MoveArgs a = make_args(desc_of(L, g), st->iter);
+    const int u = item - as_const(L.prefix_segs)[g];
     const int h = a.seg_hub[u];
     if (a.hub_act[h] == 0) continue;
     const int v = a.order[h];
@@ -1713,10 +1730,11 @@ __global__ __launch_bounds__(256) void k_hub_shared(Launch L) {
   __shared__ float val[K];
   for (int item = blockIdx.x; item < L.total_hubs; item += gridDim.x) {
     const int g = find_graph(L.prefix_hubs, L.G, item);
-    const GraphDesc &gd = L.d[g];
-    if (gd.st->done) continue;
-    const MoveArgs a = make_args(gd, gd.st->iter);
-    const int h = item - L.prefix_hubs[g];
+    const kptr<GraphStatus> st = status_of(L, g);
+    if (st->done) continue;
+    DescRef gd = desc_of(L, g);
+    const MoveArgs a = make_args(gd, st->iter);
+    const int h = item - as_const(L.prefix_hubs)[g];
     if (a.hub_act[h] == 0) continue;
     const int v = a.order[h], self = state_at(a, h, v);
     if (threadIdx.x < K) {
@@ -1744,10 +1762,10 @@ __global__ __launch_bounds__(256) void k_hub_shared(Launch L) {
       const bool moved = c != cv && (!a.pickless || c < cv);
       if (moved) {
         a.C[self] = c;
-        atomicAdd(gd.dN + gd.st->iter, 1ull);
+        atomicAdd(gd.dN + st->iter, 1ull);
       }
       a.hub_act[h] = moved ? 1 : 0;  // k_hub_mark flags the neighbours
-      atomicAdd(gd.scanned + gd.st->iter, (unsigned long long)(re - rb));
+      atomicAdd(gd.scanned + st->iter, (unsigned long long)(re - rb));
     }
     __syncthreads();
   }
