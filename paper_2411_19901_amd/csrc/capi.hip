@@ -352,7 +352,12 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 }
 
 // Sum of squares of the community totals (then cleared for the next call).
-__global__ void k_mod_sq(double *tot, int n, double *acc) {
+// One atomic per workgroup: atomics on the one accumulator serialise, so
+// the workgroup sums its wavefronts' parts first (and the launch is capped
+// at kModSqBlocks workgroups).
+constexpr int kModSqBlocks = 1024;
+__global__ __launch_bounds__(kAuxBlock) void k_mod_sq(double *tot, int n, double *acc) {
+  __shared__ double part[kAuxBlock / 64];
   double s = 0.0;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     const double x = tot[c];
@@ -360,7 +365,13 @@ __global__ void k_mod_sq(double *tot, int n, double *acc) {
     tot[c] = 0.0;
   }
   s = wave_sum_d(s);
-  if ((threadIdx.x & 63) == 0) atomicAdd(&acc[2], s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kAuxBlock / 64; ++w) t += part[w];
+    atomicAdd(&acc[2], t);
+  }
 }
 
 // Only the memory accesses of one full scan: stream col and w, gather
@@ -1857,7 +1868,7 @@ int modularity_into(lpa_handle *h, const int32_t *labels, double *q, double *tot
   m.acc = acc;
   if (h->mod_grid == 0) h->mod_grid = h->self->cus * modularity_blocks_per_cu();
   HIP_TRY(h, launch_modularity(m, h->mod_grid, h->stream));
-  hipLaunchKernelGGL(k_mod_sq, dim3(grid_for(n, kAuxBlock, 4096)), dim3(kAuxBlock), 0, h->stream,
+  hipLaunchKernelGGL(k_mod_sq, dim3(grid_for(n, kAuxBlock, kModSqBlocks)), dim3(kAuxBlock), 0, h->stream,
                      tot, n, acc);
   LAUNCH_TRY(h, "modularity kernels");
   double out[4] = {0, 0, 0, 0};

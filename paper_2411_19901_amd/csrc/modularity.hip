@@ -268,11 +268,24 @@ __global__ __launch_bounds__(kBlock) void k_modularity(ModArgs m) {
     }
   }
   if (pc >= 0 && lane == 0) atomicAdd(&m.tot[pc], ps);
+  // one pair of atomics per workgroup: atomics on the two accumulators
+  // serialise, so the workgroup sums its wavefronts' parts first
+  __shared__ double part[2][kBlock / kWave];
   k_acc = wave_sum_d(k_acc);
   in_acc = wave_sum_d(in_acc);
   if (lane == 0) {
-    atomicAdd(&m.acc[0], k_acc);
-    atomicAdd(&m.acc[1], in_acc);
+    part[0][wib] = k_acc;
+    part[1][wib] = in_acc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+      a0 += part[0][w];
+      a1 += part[1][w];
+    }
+    atomicAdd(&m.acc[0], a0);
+    atomicAdd(&m.acc[1], a1);
   }
 }
 
