@@ -1055,6 +1055,43 @@ __device__ __forceinline__ void flush_counts(unsigned long long *dN, unsigned lo
   scanned_lane = scanned_w = changed_w = 0;
 }
 
+// The last flush of a launch: every wavefront ends at once, and atomics on
+// one counter serialise, so the workgroup's wavefronts combine their counts
+// per counter (those that ended on the same graph) and one lane adds each
+// sum.  Every thread of the workgroup must call it.
+__device__ __forceinline__ void flush_last_counts(unsigned long long *dN, unsigned long long *sc,
+                                                  unsigned long long &scanned_lane,
+                                                  unsigned long long &scanned_w,
+                                                  unsigned long long &changed_w, int wib) {
+  constexpr int NW = kBlock / kWave;
+  __shared__ unsigned long long *f_dN[NW], *f_sc[NW];
+  __shared__ unsigned long long f_changed[NW], f_scanned[NW];
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) scanned_lane += __shfl_xor(scanned_lane, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    f_dN[wib] = dN;
+    f_sc[wib] = sc;
+    f_changed[wib] = changed_w;
+    f_scanned[wib] = scanned_lane + scanned_w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < NW; ++w) {
+      if (!f_dN[w]) continue;
+      unsigned long long c = f_changed[w], t = f_scanned[w];
+      for (int u = w + 1; u < NW; ++u)
+        if (f_dN[u] == f_dN[w]) {  // the same graph and iteration: the same two counters
+          c += f_changed[u];
+          t += f_scanned[u];
+          f_dN[u] = nullptr;
+        }
+      if (t) atomicAdd(f_sc[w], t);
+      if (c) atomicAdd(f_dN[w], c);
+    }
+  }
+  scanned_lane = scanned_w = changed_w = 0;
+}
+
 // Lane units keep narrow rows' column indices in the stage for marking
 // (staged_rows) only in the kernels whose wavefronts per SIMD it leaves
 // unchanged: single scan, sketch votes, 32-bit positions (k <= 8 stays
@@ -1119,7 +1156,7 @@ __device__ __forceinline__ void move_body(const Launch &L) {
     lane_units<K, ASYNC, RS, Pos, kKeepCols<K, RS, Pos, SV>>(
         a, stage[wib], lane_local * kWave + lane, scanned_lane, changed_w);
   }
-  flush_counts(cdN, csc, scanned_lane, scanned_w, changed_w);
+  flush_last_counts(cdN, csc, scanned_lane, scanned_w, changed_w, wib);
 }
 
 // CSR positions are int for graphs of fewer than 2^31 entries (W = false),
