@@ -1166,15 +1166,16 @@ template <bool W>
 using PosOf = typename std::conditional<W, long long, int>::type;
 
 // One iteration's label moves (single scan) ...  With 32-bit positions the
-// kernel fits 128 registers up to k = 8 and k = 16 in det mode, which keeps
-// four wavefronts per SIMD for the gathers, and 168 for k = 16 in async
-// mode and k = 32 in det mode (three); the other instantiations are left to
-// the compiler.
+// kernel is held to 128 registers up to k = 16, which keeps four wavefronts
+// per SIMD for the gathers (async k = 16 spills a few registers there and
+// still runs 8% faster on R-MAT-24 than with three wavefronts), and to 168
+// for k = 32 in det mode (three); the other instantiations are left to the
+// compiler.
 template <int K, bool ASYNC, bool W>
-constexpr int kMoveWaves = W                                    ? 1
-                           : (K <= 8 || (K == 16 && !ASYNC))    ? 4
-                           : (K == 16 || (K == 32 && !ASYNC))   ? 3
-                                                                : 1;
+constexpr int kMoveWaves = W                     ? 1
+                           : (K <= 16)           ? 4
+                           : (K == 32 && !ASYNC) ? 3
+                                                 : 1;
 
 template <int K, bool ASYNC, bool W>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMoveWaves<K, ASYNC, W>)))
