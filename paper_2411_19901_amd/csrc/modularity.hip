@@ -18,28 +18,45 @@ namespace lpa {
 namespace {
 
 // tot[c] += x for every lane where `on` holds.  The lanes that share the
-// first pending lane's label are summed across the wavefront and added with
-// one atomic, and so on for the next pending label, while such groups have
-// two or more lanes (at most kCombineRounds of them); every lane left adds
-// its own value.  A converged labelling puts a wavefront's vertices in a few
-// communities, whose atomics on one address would serialise, while a
-// wavefront of distinct labels gains nothing from cross-lane sums.
-constexpr int kCombineRounds = 8;
-
+// lowest active lane's label are summed across the wavefront and added
+// with one atomic (a converged labelling often gives most of a wavefront's
+// vertices one community, whose atomics on one address would serialise);
+// the other lanes are summed per run of consecutive lanes with one label
+// (vertices close in the degree order are often neighbours, so a label
+// tends to come in runs) and each run's first lane adds its sum.
 __device__ void add_by_label(double *tot, int c, double x, bool on) {
   const int lane = threadIdx.x & (kWave - 1);
   unsigned long long rest = __ballot(on);
-  for (int round = 0; round < kCombineRounds && rest; ++round) {
+  if (!rest) return;
+  {
     const int src = __ffsll((long long)rest) - 1;
     const int cs = rl(c, src);
-    const bool grp = ((rest >> lane) & 1ull) && c == cs;
+    const bool grp = on && c == cs;
     const unsigned long long gm = __ballot(grp);
-    if (!(gm & (gm - 1))) break;  // a group of one: no sums from here on
-    const double s = wave_sum_d(grp ? x : 0.0);
-    if (lane == src) atomicAdd(&tot[cs], s);
-    rest &= ~gm;
+    if (gm & (gm - 1)) {  // two or more lanes
+      const double s = wave_sum_d(grp ? x : 0.0);
+      if (lane == src) atomicAdd(&tot[cs], s);
+      rest &= ~gm;
+    }
   }
-  if ((rest >> lane) & 1ull) atomicAdd(&tot[c], x);
+  if (!rest) return;
+  // runs: a lane in `rest` continues the run of the lane below it when
+  // that lane is in `rest` with the same label; rid = the lane where the
+  // run starts (lanes outside `rest` carry 0 and join the run below them)
+  const bool mine = (rest >> lane) & 1ull;
+  const int cp = __shfl_up(c, 1);
+  const bool cont = lane > 0 && ((rest >> (lane - 1)) & 1ull) && cp == c;
+  const unsigned long long heads = __ballot(mine && !cont);
+  const unsigned long long below = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+  const int rid = 63 - __clzll(heads & below);
+  double v = mine ? x : 0.0;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const double y = __shfl_down(v, off);
+    const int ro = __shfl_down(rid, off);
+    if (lane + off < kWave && ro == rid) v += y;
+  }
+  if (mine && !cont) atomicAdd(&tot[c], v);
 }
 
 // One step of TW entries per row (TW <= T), as in the move kernel's
